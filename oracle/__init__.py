@@ -1,0 +1,228 @@
+"""FP64 CPU oracle for walk on stars -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports, links or calls anything here; the two share
+no code.  The only common inputs are the seeded scene arrays from ``scenes``.
+
+``wost_oracle.c`` is a brute-force, uniform-sampling FP64 WoSt (built with gcc
++ OpenMP by :func:`build`); ``guide_ref`` holds FP64 reference definitions of
+the guiding distribution (vMF mixture, reflection, MIS, samplers, network and
+training loss).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wost_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle (gcc, -O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+               "-Wno-misleading-indentation", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Field(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_int), ("params", C.POINTER(C.c_double))]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("g", _Field), ("h", _Field), ("f", _Field),
+                ("eps", C.c_double), ("r_min", C.c_double),
+                ("max_steps", C.c_int32), ("rr_start", C.c_int32), ("rr_q", C.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = C.CDLL(_LIB)
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    lib.or_scene_create.restype = P
+    lib.or_scene_create.argtypes = [C.c_int, dp, C.c_int64, C.POINTER(C.c_int32), C.c_int64,
+                                    C.POINTER(C.c_uint8)]
+    lib.or_scene_free.argtypes = [P]
+    lib.or_scene_n_silhouette_candidates.restype = C.c_int64
+    lib.or_scene_n_silhouette_candidates.argtypes = [P]
+    lib.or_solve.restype = C.c_int
+    lib.or_solve.argtypes = [P, C.POINTER(_Problem), dp, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
+                             dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                             dp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int]
+    lib.or_walk_trace.restype = C.c_int32
+    lib.or_walk_trace.argtypes = [P, C.POINTER(_Problem), dp, C.c_uint64, C.c_uint32, C.c_uint32,
+                                  dp, dp, C.c_int32, dp, dp, C.POINTER(C.c_int32)]
+    lib.or_closest_dirichlet.argtypes = [P, dp, C.c_int64, dp, dp]
+    lib.or_silhouette.argtypes = [P, dp, C.c_int64, dp]
+    lib.or_ray_neumann.argtypes = [P, dp, dp, dp, C.c_int64, dp, C.POINTER(C.c_int64)]
+    lib.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+    lib.or_green_ball.restype = C.c_double
+    lib.or_green_ball.argtypes = [C.c_int, C.c_double, C.c_double]
+    lib.or_field_value.restype = C.c_double
+    lib.or_field_value.argtypes = [C.c_int, C.c_int, dp, C.c_int, dp]
+    _lib = lib
+    return lib
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def philox4x32_10(ctr, key):
+    lib = _load()
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    o = np.zeros(4, np.uint32)
+    lib.or_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(o, C.c_uint32))
+    return o
+
+
+def green_ball(d, r, rho):
+    return _load().or_green_ball(d, r, rho)
+
+
+def field_value(field, dim, x):
+    kind, params = field
+    params = np.ascontiguousarray(params, np.float64).ravel()
+    n = int(params.size // (2 + dim)) if kind == 6 else int(params.size)
+    x = np.ascontiguousarray(x, np.float64)
+    return _load().or_field_value(int(kind), n, _ptr(params, C.c_double) if params.size else None,
+                                  dim, _ptr(x, C.c_double))
+
+
+class OracleScene:
+    """Exhaustive FP64 scene built from the seeded arrays of a ``scenes.Scene``."""
+
+    def __init__(self, scene):
+        lib = _load()
+        self.scene = scene
+        self.dim = scene.dim
+        self._v = np.ascontiguousarray(scene.verts, np.float64)
+        self._p = np.ascontiguousarray(scene.prims, np.int32)
+        self._b = np.ascontiguousarray(scene.bc, np.uint8)
+        self.h = lib.or_scene_create(self.dim, _ptr(self._v, C.c_double), self._v.shape[0],
+                                     _ptr(self._p, C.c_int32), self._p.shape[0], _ptr(self._b, C.c_uint8))
+        if not self.h:
+            raise ValueError("or_scene_create failed")
+        self._keep = []
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_scene_free(self.h)
+            self.h = None
+
+    @property
+    def n_silhouette_candidates(self):
+        return _load().or_scene_n_silhouette_candidates(self.h)
+
+    def _problem(self, eps=None, r_min=None, max_steps=None, rr_start=None, rr_q=None):
+        s = self.scene
+        keep = []
+
+        def fld(fd):
+            kind, params = fd
+            params = np.ascontiguousarray(params, np.float64).ravel()
+            keep.append(params)
+            n = int(params.size // (2 + self.dim)) if kind == 6 else int(params.size)
+            return _Field(int(kind), n, _ptr(params, C.c_double) if params.size else None)
+
+        eps = s.eps if eps is None else eps
+        pb = _Problem(fld(s.g), fld(s.h), fld(s.f), eps, eps if r_min is None else r_min,
+                      s.max_steps if max_steps is None else max_steps,
+                      s.rr_start if rr_start is None else rr_start,
+                      s.rr_q if rr_q is None else rr_q)
+        self._keep = keep
+        return pb
+
+    def solve(self, points=None, wpp=None, seed=18944, walk_offset=0, per_walk=False,
+              nthreads=0, **problem_kw):
+        lib = _load()
+        pts = np.ascontiguousarray(self.scene.points if points is None else points, np.float64)
+        n = pts.shape[0]
+        wpp = self.scene.wpp if wpp is None else wpp
+        pb = self._problem(**problem_kw)
+        su = np.zeros(n)
+        sq = np.zeros(n)
+        cnt = np.zeros(n, np.int64)
+        st = np.zeros(n, np.int64)
+        wv = ws = wst = None
+        if per_walk:
+            wv = np.zeros(n * wpp)
+            ws = np.zeros(n * wpp, np.int32)
+            wst = np.zeros(n * wpp, np.int32)
+        rc = lib.or_solve(self.h, C.byref(pb), _ptr(pts, C.c_double), n, wpp, seed, walk_offset,
+                          _ptr(su, C.c_double), _ptr(sq, C.c_double), _ptr(cnt, C.c_int64),
+                          _ptr(st, C.c_int64),
+                          _ptr(wv, C.c_double) if per_walk else None,
+                          _ptr(ws, C.c_int32) if per_walk else None,
+                          _ptr(wst, C.c_int32) if per_walk else None, nthreads)
+        if rc != 0:
+            raise RuntimeError("or_solve failed")
+        out = {"sum": su, "sumsq": sq, "count": cnt, "steps": st}
+        if per_walk:
+            out.update(walk_value=wv, walk_steps=ws, walk_status=wst)
+        return out
+
+    def walk_trace(self, x0, p, j, seed=18944, cap=1 << 16, **problem_kw):
+        lib = _load()
+        pb = self._problem(**problem_kw)
+        x0 = np.ascontiguousarray(x0, np.float64)
+        c = np.zeros(cap)
+        w = np.zeros(cap)
+        val = C.c_double()
+        term = C.c_double()
+        status = C.c_int32()
+        n = lib.or_walk_trace(self.h, C.byref(pb), _ptr(x0, C.c_double), seed, p, j,
+                              _ptr(c, C.c_double), _ptr(w, C.c_double), cap,
+                              C.byref(val), C.byref(term), C.byref(status))
+        return {"c": c[:n], "w": w[:n], "value": val.value, "terminal": term.value,
+                "status": status.value}
+
+    def closest_dirichlet(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        n = x.shape[0]
+        d = np.zeros(n)
+        xb = np.zeros_like(x)
+        _load().or_closest_dirichlet(self.h, _ptr(x, C.c_double), n, _ptr(d, C.c_double),
+                                     _ptr(xb, C.c_double))
+        return d, xb
+
+    def silhouette(self, x):
+        x = np.ascontiguousarray(x, np.float64)
+        d = np.zeros(x.shape[0])
+        _load().or_silhouette(self.h, _ptr(x, C.c_double), x.shape[0], _ptr(d, C.c_double))
+        return d
+
+    def ray_neumann(self, x, nu, tmax):
+        x = np.ascontiguousarray(x, np.float64)
+        nu = np.ascontiguousarray(nu, np.float64)
+        tmax = np.ascontiguousarray(np.broadcast_to(tmax, (x.shape[0],)), np.float64)
+        t = np.zeros(x.shape[0])
+        pr = np.zeros(x.shape[0], np.int64)
+        _load().or_ray_neumann(self.h, _ptr(x, C.c_double), _ptr(nu, C.c_double),
+                               _ptr(tmax, C.c_double), x.shape[0], _ptr(t, C.c_double),
+                               _ptr(pr, C.c_int64))
+        return t, pr
+
+
+def estimates(res):
+    """Per-point mean, standard error and count from accumulated sums."""
+    n = res["count"].astype(np.float64)
+    mean = res["sum"] / n
+    var = np.maximum(res["sumsq"] / n - mean * mean, 0.0) * n / np.maximum(n - 1, 1)
+    return mean, np.sqrt(var / n), n
