@@ -58,6 +58,7 @@ def _load():
     lib.or_scene_create.argtypes = [C.c_int, dp, C.c_int64, C.POINTER(C.c_int32), C.c_int64,
                                     C.POINTER(C.c_uint8)]
     lib.or_scene_free.argtypes = [P]
+    lib.or_scene_set_tolerance.argtypes = [P, C.c_double]
     lib.or_scene_n_silhouette_candidates.restype = C.c_int64
     lib.or_scene_n_silhouette_candidates.argtypes = [P]
     lib.or_solve.restype = C.c_int
@@ -71,6 +72,8 @@ def _load():
     lib.or_silhouette.argtypes = [P, dp, C.c_int64, dp]
     lib.or_ray_neumann.argtypes = [P, dp, dp, dp, C.c_int64, dp, C.POINTER(C.c_int64)]
     lib.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+    lib.or_philox4x32_10_batch.argtypes = [C.POINTER(C.c_uint32), C.c_int64, C.POINTER(C.c_uint32),
+                                           C.POINTER(C.c_uint32)]
     lib.or_green_ball.restype = C.c_double
     lib.or_green_ball.argtypes = [C.c_int, C.c_double, C.c_double]
     lib.or_field_value.restype = C.c_double
@@ -92,6 +95,16 @@ def philox4x32_10(ctr, key):
     return o
 
 
+def philox_batch(ctr, key):
+    """ctr uint32 [n, 4] -> Philox4x32-10 outputs [n, 4]."""
+    lib = _load()
+    c = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    k = np.ascontiguousarray(key, np.uint32)
+    o = np.zeros_like(c)
+    lib.or_philox4x32_10_batch(_ptr(c, C.c_uint32), c.shape[0], _ptr(k, C.c_uint32), _ptr(o, C.c_uint32))
+    return o
+
+
 def green_ball(d, r, rho):
     return _load().or_green_ball(d, r, rho)
 
@@ -108,7 +121,7 @@ def field_value(field, dim, x):
 class OracleScene:
     """Exhaustive FP64 scene built from the seeded arrays of a ``scenes.Scene``."""
 
-    def __init__(self, scene):
+    def __init__(self, scene, tau_rel=None):
         lib = _load()
         self.scene = scene
         self.dim = scene.dim
@@ -119,6 +132,8 @@ class OracleScene:
                                      _ptr(self._p, C.c_int32), self._p.shape[0], _ptr(self._b, C.c_uint8))
         if not self.h:
             raise ValueError("or_scene_create failed")
+        if tau_rel is not None:
+            lib.or_scene_set_tolerance(self.h, float(tau_rel))
         self._keep = []
 
     def __del__(self):

@@ -35,6 +35,7 @@ import torch
 
 KAPPA_LOG_MIN = -10.0
 KAPPA_LOG_MAX = 9.0
+C_LOGIT = 15.0       # |c'| clamp of the selection-probability logit
 E_MIS = 0.2          # fixed fraction e of the selection-probability loss (Sec. 4.4)
 HASH_PRIMES = (1, 2654435761, 805459861)
 
@@ -106,7 +107,7 @@ def map_outputs(y, d, K):
     lp = lob[..., d + 1]
     lam = np.exp(lp - lp.max(axis=-1, keepdims=True))
     lam /= lam.sum(axis=-1, keepdims=True)
-    c = 1.0 / (1.0 + np.exp(-y[..., K * (d + 2)]))
+    c = 1.0 / (1.0 + np.exp(-np.clip(y[..., K * (d + 2)], -C_LOGIT, C_LOGIT)))
     return mu, kappa, lam, c
 
 
@@ -241,16 +242,24 @@ class GuideConfig:
 def grid_corners(cfg: GuideConfig, x):
     """Per level: integer corner indices [n, 2^d] into the level table and the
     multilinear weights [n, 2^d] (equation "G": interpolation of the embeddings
-    at the corners of the enclosing cell, levels concatenated)."""
-    x = np.asarray(x, float)
+    at the corners of the enclosing cell, levels concatenated).
+
+    The cell index is an integer decided by floating point, so the normalised
+    position, cell and fractional offsets are computed in float32 with the
+    same operation order as a float32 implementation would (reading listed
+    in the design doc); the weights are then used in float64."""
+    f = np.float32
+    x = np.asarray(x, float).astype(f)
     d = cfg.dim
-    xh = np.clip((x - cfg.lo) / (cfg.hi - cfg.lo), 0.0, 1.0)
+    lo = np.asarray(cfg.lo, float).astype(f)
+    inv_ext = (f(1.0) / (np.asarray(cfg.hi, float).astype(f) - lo)).astype(f)
+    xh = np.minimum(np.maximum((x - lo) * inv_ext, f(0.0)), f(1.0)).astype(f)
     out = []
     for l in range(cfg.L):
         N = cfg.resolution(l)
-        pos = xh * N
-        cell = np.minimum(np.floor(pos), N - 1).astype(np.int64)
-        fr = pos - cell
+        pos = (xh * f(N)).astype(f)
+        cell = np.clip(np.floor(pos), 0, N - 1).astype(np.int64)
+        fr = (pos - cell.astype(f)).astype(f).astype(np.float64)
         dense = (N + 1) ** d <= cfg.T
         idx = []
         wts = []
@@ -299,13 +308,25 @@ def encode(cfg: GuideConfig, grid, x):
     return torch.cat(feats, dim=1)
 
 
-def forward(cfg: GuideConfig, params, x):
-    """NN(x | Phi): raw outputs y [n, K(d+2)+1] in float64 (no intermediate rounding)."""
+def _round_half(t):
+    """Round to the nearest fp16 value, keeping float64 (gradient passes through)."""
+    return t + (t.to(torch.float16).to(torch.float64) - t).detach()
+
+
+def forward(cfg: GuideConfig, params, x, round_inputs=False):
+    """NN(x | Phi): raw outputs y [n, K(d+2)+1] in float64.  With
+    ``round_inputs`` every layer input (grid features, hidden activations) is
+    rounded to fp16 first -- the points where a half-precision network rounds;
+    the arithmetic stays float64."""
     params = torch.as_tensor(params, dtype=torch.float64)
     grid, Ws = split_params(cfg, params)
     h = encode(cfg, grid, x)
     for W in Ws[:-1]:
+        if round_inputs:
+            h = _round_half(h)
         h = torch.relu(h @ W)
+    if round_inputs:
+        h = _round_half(h)
     return h @ Ws[-1]
 
 
@@ -337,7 +358,7 @@ def loss_per_sample(cfg: GuideConfig, y, nu, n_in, on_n, p_sample, p_t, e=E_MIS,
     mu = mup / mup.norm(dim=-1, keepdim=True)
     kappa = torch.exp(torch.clamp(lob[..., d], KAPPA_LOG_MIN, KAPPA_LOG_MAX))
     loglam = torch.log_softmax(lob[..., d + 1], dim=-1)
-    c = torch.sigmoid(y[:, K * (d + 2)])
+    cl = torch.clamp(y[:, K * (d + 2)], -C_LOGIT, C_LOGIT)
     l1 = loglam + log_vmf_t(nu_t[:, None, :], mu, kappa, d)                       # [n, K]
     nu_r = nu_t - 2.0 * (nu_t * n_t).sum(-1, keepdim=True) * n_t
     l2 = loglam + log_vmf_t(nu_r[:, None, :], mu, kappa, d)
@@ -346,14 +367,16 @@ def loss_per_sample(cfg: GuideConfig, y, nu, n_in, on_n, p_sample, p_t, e=E_MIS,
     log_pg = torch.where(on, both, one)
     area = sphere_area(d)
     pu = torch.where(on, torch.full_like(log_pg, 2.0 / area), torch.full_like(log_pg, 1.0 / area))
-    pg_sg = torch.exp(log_pg).detach() if pg_fixed is None else _t(pg_fixed)
-    log_pmis = torch.log(c * pg_sg + (1.0 - c) * pu)
+    log_pg_sg = log_pg.detach() if pg_fixed is None else torch.log(_t(pg_fixed))
+    # log(c sg(p_g) + (1 - c) p_u) with log c = -softplus(-c'), log(1 - c) = -softplus(c')
+    log_pmis = torch.logaddexp(-torch.nn.functional.softplus(-cl) + log_pg_sg,
+                               -torch.nn.functional.softplus(cl) + torch.log(pu))
     w = _t(p_t) / _t(p_sample)
     return -w * (log_pg + e * log_pmis)
 
 
-def loss(cfg: GuideConfig, params, x, nu, n_in, on_n, p_sample, p_t, e=E_MIS, pg_fixed=None):
-    y = forward(cfg, params, x)
+def loss(cfg: GuideConfig, params, x, nu, n_in, on_n, p_sample, p_t, e=E_MIS, pg_fixed=None, round_inputs=False):
+    y = forward(cfg, params, x, round_inputs)
     return loss_per_sample(cfg, y, nu, n_in, on_n, p_sample, p_t, e, pg_fixed).mean()
 
 
@@ -366,9 +389,9 @@ def guiding_pdf_of_params(cfg: GuideConfig, params, x, nu, n_in, on_n):
                      for i in range(len(nu))])
 
 
-def loss_and_grad(cfg: GuideConfig, params, x, nu, n_in, on_n, p_sample, p_t, e=E_MIS):
+def loss_and_grad(cfg: GuideConfig, params, x, nu, n_in, on_n, p_sample, p_t, e=E_MIS, round_inputs=False):
     p = torch.tensor(np.asarray(params, float), dtype=torch.float64, requires_grad=True)
-    L = loss(cfg, p, x, nu, n_in, on_n, p_sample, p_t, e)
+    L = loss(cfg, p, x, nu, n_in, on_n, p_sample, p_t, e, round_inputs=round_inputs)
     L.backward()
     return float(L.detach()), p.grad.numpy().copy()
 

@@ -59,7 +59,6 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 
 static double u01(uint32_t w) { return (double)(w >> 8) * (1.0 / 16777216.0); }
 /* (0, 1] variant for logarithms */
-static double u01oc(uint32_t w) { return (double)((w >> 8) + 1u) * (1.0 / 16777216.0); }
 
 typedef struct {
     uint32_t key[2];
@@ -410,7 +409,6 @@ static int visible(const or_scene* s, const double* x, const double* z, int64_t 
 
 /* ------------------------------------------------------------------ kernels */
 
-static double sphere_area(int d) { return d == 2 ? 2.0 * OR_PI : 4.0 * OR_PI; }
 
 /* Green's function of the ball of radius r (zero Dirichlet on its sphere),
    -Laplacian G = delta, at distance rho from the centre */
@@ -663,4 +661,15 @@ double or_field_value(int kind, int n, const double* params, int dim, const doub
 {
     or_field f = {kind, n, params};
     return field_value(&f, dim, x);
+}
+
+/* Facing / self-intersection tolerance relative to the AABB diagonal (default
+   1e-12).  Query-parity tests set the GPU path's FP32 tolerance here so that
+   both sides take facing decisions with the same margin. */
+void or_scene_set_tolerance(or_scene* s, double tau_rel) { s->tau = tau_rel * s->L; }
+
+/* Batched Philox4x32-10: out[i] = philox(ctr[i], key) for i < n. */
+void or_philox4x32_10_batch(const uint32_t* ctr, int64_t n, const uint32_t key[2], uint32_t* out)
+{
+    for (int64_t i = 0; i < n; ++i) or_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
 }

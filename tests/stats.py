@@ -14,12 +14,18 @@ import numpy as np
 from scipy import stats
 
 
-def zscore_check(mean, se, ref, n_walks, bias_slack=0.0, var_band=(0.75, 1.35), label=""):
+def zscore_check(mean, se, ref, n_walks, bias_slack=0.0, var_band=(0.75, 1.35), label="", allow=None):
+    """``allow`` is an optional per-point bias allowance (e.g. the epsilon-shell
+    bias eps |grad u|): deviations are shrunk by it before dividing by se."""
     mean = np.asarray(mean, float)
     se = np.asarray(se, float)
     ref = np.asarray(ref, float)
     ok = se > 0
-    z = (mean[ok] - ref[ok]) / se[ok]
+    dev = mean[ok] - ref[ok]
+    if allow is not None:
+        a = np.asarray(allow, float)[ok]
+        dev = np.sign(dev) * np.maximum(np.abs(dev) - a, 0.0)
+    z = dev / se[ok]
     N = z.size
     dof = max(int(np.min(n_walks)) - 1, 3)
     p3 = 2.0 * stats.t.sf(3.0, dof)

@@ -257,7 +257,9 @@ def test_grid_dense_levels_reproduce_linear_functions():
     f = G.encode(cfg, grid, x).numpy()
     xh = (x + 1) / 2
     for l in range(cfg.L):
-        np.testing.assert_allclose(f[:, 2 * l], 2.0 * xh[:, 0] - 0.5 * xh[:, 1], atol=1e-12)
+        # lattice decisions are taken in float32: exact up to float32 rounding
+        # of the normalised position (a wrong corner or weight errs by ~1/N)
+        np.testing.assert_allclose(f[:, 2 * l], 2.0 * xh[:, 0] - 0.5 * xh[:, 1], atol=1e-6)
         np.testing.assert_allclose(f[:, 2 * l + 1], 1.0, atol=1e-12)
 
 
