@@ -1,0 +1,314 @@
+/*
+ * wost.h -- C ABI of the MI355X (gfx950) guided walk-on-stars library.
+ *
+ * The library estimates the solution u of the mixed Poisson problem
+ *     Laplacian u = f  in the domain,  u = g on the Dirichlet part,
+ *     du/dn = h on the Neumann part
+ * (paper Sec. 3.1, equation "linear_elliptic") at query points by the walk on
+ * stars estimator (Sec. 3.2, equation "wost_estm"), with the recursive term's
+ * direction drawn uniformly or from a learned von Mises-Fisher mixture
+ * combined with uniform sampling by one-sample MIS (Secs. 4.1-4.4).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ * - Status: every int-returning call returns WOST_OK (0) or a negative
+ *   WOST_E* code; wost_last_error() then holds a thread-local message.
+ *   Nothing throws across the ABI, nothing aborts or exits.
+ * - Memory: device buffers are allocated by the CALLER (e.g. as torch
+ *   tensors) and passed as raw device pointers; the library never allocates
+ *   device memory.  Size queries (*_bytes) tell the caller what to allocate.
+ *   Host pointers are only read during the call unless stated otherwise.
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *   stream).  Launches are asynchronous on that stream; nothing synchronises
+ *   except wost_build_bvh (host-only) and wost_geom_upload (host->device copy).
+ * - Layouts: points and directions are row-major [n][dim] float32 (AoS).
+ * - Handles are not thread-safe; distinct handles may be used concurrently.
+ */
+#ifndef WOST_H
+#define WOST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define WOST_OK 0
+#define WOST_EINVAL (-1)        /* invalid argument (NULL, out-of-range, bad shape)   */
+#define WOST_ESIZE (-2)         /* caller buffer too small                             */
+#define WOST_EHIP (-3)          /* a HIP runtime call failed                           */
+#define WOST_ESTATE (-4)        /* handle in the wrong state (e.g. not uploaded/bound) */
+#define WOST_EUNSUPPORTED (-5)  /* valid but unsupported configuration                 */
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* wost_last_error(void);
+
+/* Opaque handles. */
+typedef struct wost_geom wost_geom;     /* boundary hierarchies          */
+typedef struct wost_guide wost_guide;   /* neural guiding field          */
+
+/* ------------------------------------------------------------ fields
+ * Analytic fields for the boundary data g, h and the source f.
+ *   WOST_FIELD_ZERO        0
+ *   WOST_FIELD_CONST       params[0]
+ *   WOST_FIELD_EXP_SIN     e^x sin y
+ *   WOST_FIELD_RE_Z3       Re z^3 = x^3 - 3 x y^2
+ *   WOST_FIELD_X2_MINUS_Y2 x^2 - y^2
+ *   WOST_FIELD_R2          |x|^2
+ *   WOST_FIELD_GAUSS_SUM   sum_j a_j exp(-|x - c_j|^2 / (2 s_j^2)),
+ *                          params = n rows of (a_j, s_j, c_j[dim]); n <= 32
+ * For the Neumann data h, a CONST kind is the outward flux du/dn_out itself and
+ * any other kind phi means h = grad(phi) . n_out (outward normal derivative).
+ * params is a HOST pointer read during the call. */
+#define WOST_FIELD_ZERO 0
+#define WOST_FIELD_CONST 1
+#define WOST_FIELD_EXP_SIN 2
+#define WOST_FIELD_RE_Z3 3
+#define WOST_FIELD_X2_MINUS_Y2 4
+#define WOST_FIELD_R2 5
+#define WOST_FIELD_GAUSS_SUM 6
+#define WOST_MAX_GAUSS 32
+
+typedef struct {
+    int32_t kind;
+    int32_t n;              /* number of parameter rows (GAUSS_SUM) or values */
+    const float* params;    /* host */
+} wost_field;
+
+/* ------------------------------------------------------------ geometry
+ * wost_build_bvh: host-side build of the boundary representation.
+ *   dim      2 (polyline segments) or 3 (triangles)
+ *   verts    host float32 [n_verts][dim]
+ *   prims    host int32 [n_prims][dim] vertex ids.  Winding: in 2D the domain
+ *            lies to the LEFT of each directed segment a->b; in 3D (b-a)x(c-a)
+ *            points OUT of the domain.
+ *   bc       host uint8 [n_prims]: 0 = Dirichlet, 1 = Neumann
+ *   opts     NULL for defaults
+ * Builds bounding volume hierarchies over the Dirichlet primitives (closest
+ * point, Sec. 3.2), the Neumann primitives (rays, visibility, Neumann-term
+ * sampling) and the Neumann silhouette candidates -- vertices in 2D, edges in
+ * 3D -- with normal cones (closest silhouette; the star radius of Sec. 3.2).
+ * Degenerate primitives (zero length / area) and out-of-range vertex ids
+ * give WOST_EINVAL.  On success *out owns a host image of the device layout. */
+typedef struct {
+    int32_t leaf_size;      /* max primitives per leaf (default 4, 1..64)             */
+    int32_t brute_force;    /* 1: a single leaf per hierarchy (exhaustive queries)     */
+} wost_build_opts;
+
+int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, const int32_t* prims,
+                   int64_t n_prims, const uint8_t* bc, const wost_build_opts* opts, wost_geom** out);
+/* Bytes of device memory the geometry needs (256-byte aligned base required). */
+int64_t wost_geom_device_bytes(const wost_geom* geom);
+/* Copy the geometry into the caller-owned device buffer `dev_buf` (>= bytes)
+ * on `stream`, and synchronise that stream.  The buffer must outlive every
+ * call that uses `geom`.  Re-uploading to another buffer is allowed. */
+int wost_geom_upload(wost_geom* geom, void* dev_buf, int64_t bytes, void* stream);
+/* Scene statistics: out[0..7] = dim, n_dirichlet, n_neumann, n_silhouette,
+ * max BVH depth, AABB diagonal, bytes, 0. */
+int wost_geom_info(const wost_geom* geom, double* out8);
+/* Map a library-internal primitive id (as returned by wost_query) to the
+ * caller's primitive index; returns -1 if out of range. */
+int64_t wost_geom_prim_index(const wost_geom* geom, int32_t internal_id);
+void wost_geom_free(wost_geom* geom);
+
+/* Batched geometric queries of the walk (for inspection and parity tests).
+ *   pts          device [n][dim]
+ *   d_dir, xbar  device [n], [n][dim]: distance to / closest point on the
+ *                Dirichlet boundary (Sec. 3.2 epsilon-shell test); NULL to skip
+ *   d_sil        device [n]: distance to the closest Neumann silhouette point
+ *                seen from pts (the second bound of the star radius); NULL to skip
+ *   ray_dir, ray_tmax  device [n][dim] unit directions, [n] max distance; with
+ *                ray_t [n] and ray_prim [n] (caller primitive index, -1 = miss)
+ *                gives the first Neumann hit in (tau, tmax); NULL to skip.
+ * Missing results are +inf. */
+int wost_query(const wost_geom* geom, const float* pts, int64_t n, float* d_dir, float* xbar,
+               float* d_sil, const float* ray_dir, const float* ray_tmax, float* ray_t,
+               int32_t* ray_prim, void* stream);
+
+/* ------------------------------------------------------------ problem + solve */
+#define WOST_SAMPLING_UNIFORM 0      /* original WoSt: uniform directions (c = 0)       */
+#define WOST_SAMPLING_MIS_LEARNED 1  /* MIS with the guide's learned c(x) (Sec. 4.4)    */
+#define WOST_SAMPLING_MIS_FIXED 2    /* MIS with c = c_fixed                             */
+#define WOST_SAMPLING_GUIDED_ONLY 3  /* c = 1                                            */
+
+typedef struct {
+    wost_field g;           /* Dirichlet value, evaluated at the closest point          */
+    wost_field h;           /* Neumann data (outward derivative), see fields above       */
+    wost_field f;           /* source with Laplacian u = f                               */
+    float eps;              /* epsilon-shell width (Sec. 3.2)                            */
+    float r_min;            /* lower clamp of the star radius (0 = use eps)              */
+    int32_t max_steps;      /* step cap; the walk then takes g at the closest point      */
+    int32_t rr_start;       /* Russian roulette from this step on (Sec. 6.1: 128)       */
+    float rr_q;             /* roulette survival probability                             */
+    int32_t sampling;       /* WOST_SAMPLING_*                                           */
+    float c_fixed;          /* selection probability for WOST_SAMPLING_MIS_FIXED         */
+    int32_t reflect;        /* 1: reflect invalid draws at Neumann points (Sec. 4.3)     */
+} wost_problem;
+
+/* Training records written by guided walks (one per drawn direction), in a
+ * caller-owned device buffer of `capacity` rows, structure-of-arrays:
+ * field f of row i is at data[f * capacity + i].  Fields (dim = d):
+ *   0..d-1     x_k           walk location
+ *   d..2d-1    nu_k          drawn direction (after reflection)
+ *   2d..3d-1   n_k           unit normal on the walk's side if x_k is on the
+ *                            Neumann boundary, else 0
+ *   3d         p_sample      MIS pdf of nu_k at draw time
+ *   3d+1       prefix        sum of T_j (N_j + S_j) over j <= k
+ *   3d+2       T_next        throughput T_{k+1} = T_k w_k (roulette folded in)
+ *   3d+3       slot          walk slot (int32 bits) in the call's walk order
+ *   3d+4       p_t           training target |V_{k+1}|, filled by
+ *                            wost_tail_pass (Sec. 4.1 target distribution)
+ * `count` is a device int64 counter of rows appended (may exceed capacity:
+ * rows beyond capacity are dropped and counted in dev_counters[6]). */
+#define WOST_REC_FIELDS(d) (3 * (d) + 5)
+typedef struct {
+    float* data;            /* device [WOST_REC_FIELDS(d)][capacity] */
+    int64_t capacity;
+    int64_t* count;         /* device */
+} wost_records;
+
+/* Workspace bytes needed by wost_solve for n_points x wpp walks. */
+int64_t wost_solve_workspace_bytes(const wost_geom* geom, int64_t n_points, int32_t wpp);
+
+/* Walk-on-stars solve (Sec. 3.2 estimator; Sec. 4 guided directions).
+ *   pts         device [n_points][dim] query points
+ *   wpp         walks per point; walk (p, j) uses Philox4x32-10 keyed by `seed`
+ *               with counter (p, walk_offset + j, step, block), so results do
+ *               not depend on how walks are split over calls
+ *   guide       NULL iff problem->sampling == WOST_SAMPLING_UNIFORM
+ *   sum, sum_sq, count   device [n_points] float64 / int64, ACCUMULATED (+=)
+ *               with the per-point sum of walk values, of squares, and walks
+ *   walk_value  device [n_points*wpp] float32 or NULL: per-walk estimate,
+ *               index p*wpp + j
+ *   walk_steps  device [n_points*wpp] int32 or NULL: stars visited per walk
+ *   rec         NULL, or training records to append (guided runs)
+ *   workspace   device, >= wost_solve_workspace_bytes
+ *   dev_counters device uint64 [8], ACCUMULATED: steps, walks, truncated
+ *               (step cap), roulette kills, non-finite weights, records,
+ *               records dropped, 0.
+ * Every walk step visits one star: closest Dirichlet point (epsilon-shell
+ * termination, Sec. 3.2), closest Neumann silhouette -> radius r, Neumann
+ * and source contributions, direction draw, first hit inside the star. */
+int wost_solve(const wost_geom* geom, const wost_problem* problem, const float* pts,
+               int64_t n_points, int32_t wpp, uint64_t seed, uint64_t walk_offset,
+               const wost_guide* guide, double* sum, double* sum_sq, int64_t* count,
+               float* walk_value, int32_t* walk_steps, const wost_records* rec, void* workspace,
+               int64_t ws_bytes, uint64_t* dev_counters, void* stream);
+
+/* ------------------------------------------------------------ guide
+ * The neural field of Sec. 5.2: a multi-resolution grid (hashed where a
+ * level's dense lattice exceeds the table) followed by a bias-free ReLU MLP
+ * whose K*(dim+2)+1 outputs are mapped by Tab. "reg_map" to K vMF lobes
+ * (mu, kappa, lambda) and the MIS selection probability c (Sec. 4.4). */
+typedef struct {
+    int32_t dim;            /* 2 or 3                                         */
+    int32_t levels;         /* L                                              */
+    int32_t feats;          /* F (must be 2)                                  */
+    int32_t log2_table;     /* log2 of entries per level                      */
+    int32_t n_min, n_max;   /* coarsest / finest lattice resolution           */
+    int32_t hidden;         /* width (must be 64)                             */
+    int32_t n_hidden;       /* hidden layers (1..4)                           */
+    int32_t K;              /* lobes (1..16)                                  */
+    float aabb_lo[3];       /* input normalisation box                        */
+    float aabb_hi[3];
+} wost_guide_config;
+
+int wost_guide_create(const wost_guide_config* cfg, wost_guide** out);
+/* Number of trainable parameters P (grid entries * F + MLP weights).  The
+ * flat float32 layout is: grid [L][T][F], then each layer's weight matrix
+ * row-major [in][out] (first layer in = L*F, hidden width 64, last out =
+ * K*(dim+2)+1; per lobe (mu'_1..mu'_dim, kappa', lambda'), then c'). */
+int64_t wost_guide_param_count(const wost_guide* g);
+/* Bytes of the half-precision shadow used by inference (grid entries in the
+ * same order, MLP weights re-arranged into MFMA operand fragments). */
+int64_t wost_guide_shadow_bytes(const wost_guide* g);
+/* Bind caller-owned device storage: master float32 [P], shadow
+ * [wost_guide_shadow_bytes] (8-byte aligned), Adam moments m, v float32 [P],
+ * gradient float32 [P].  Any of adam_m/adam_v/grad may be NULL for
+ * inference-only use.  Pointers must stay valid while the guide is used. */
+int wost_guide_bind(wost_guide* g, float* master, void* shadow_f16, float* adam_m, float* adam_v,
+                    float* grad);
+/* Seeded initialisation of master, shadow, and zeroing of Adam state:
+ * grid U(-1e-4, 1e-4), MLP He-uniform. */
+int wost_guide_init(wost_guide* g, uint64_t seed, void* stream);
+/* Refresh the fp16 shadow from the float32 master parameters. */
+int wost_guide_sync_shadow(wost_guide* g, void* stream);
+/* Raw network outputs (before the normalisation mapping) at n points:
+ * pts device [n][dim], out_raw device [n][K*(dim+2)+1]. */
+int wost_guide_infer(const wost_guide* g, const float* pts, int64_t n, float* out_raw, void* stream);
+/* One MIS direction draw per point, exactly as the walk draws it at step 0
+ * of walk (i, walk_index) with Philox key `seed`: pts device [n][dim];
+ * normals device [n][dim] or NULL -- a nonzero row marks a point on the
+ * Neumann boundary with that unit normal on the walk's side (draws are then
+ * reflected into the valid half, Sec. 4.3); sampling is a guided
+ * WOST_SAMPLING_* mode.  Outputs: out_nu [n][dim], out_pdf [n] = the MIS pdf
+ * c p_g + (1 - c) p_u of the returned direction (Sec. 4.4). */
+int wost_guide_sample(const wost_guide* g, int32_t sampling, float c_fixed, const float* pts,
+                      const float* normals, int64_t n, uint64_t seed, uint32_t walk_index, float* out_nu,
+                      float* out_pdf, void* stream);
+void wost_guide_free(wost_guide* g);
+
+/* ------------------------------------------------------------ training
+ * Online learning of the guide (Sec. 5.2 "Online Training Scheme").  The
+ * per-record loss is
+ *     l = -w [ log p_g(nu | Theta(x)) + e log( c sg(p_g) + (1 - c) p_u ) ],
+ *     w = p_t / p_sample,
+ * whose gradient w.r.t. Theta is the one-sample KL gradient of Sec. 4.2
+ * (equation "one_sample_kld", with p_g the reflected mixture on Neumann
+ * points, Sec. 4.3) and w.r.t. c the selection-probability gradient of
+ * Sec. 4.4 (equation "one_sample_sp"); sg is stop-gradient.  Records are
+ * rows [begin, begin + count) of a wost_records buffer. */
+typedef struct {
+    float lr;               /* learning rate                                 */
+    float beta1, beta2;     /* Adam moment decay rates                       */
+    float eps;              /* Adam epsilon                                  */
+    float e_mis;            /* fixed fraction e of the selection loss (0.2)  */
+} wost_adam;
+
+/* Fill the p_t field of every written record: p_t = |U - prefix| / T_next,
+ * the walk's tail estimate of u at the next location (the reverse recursion
+ * V_{k+1} of the walk's estimate), where U = walk_value[slot] is the final
+ * estimate of the walk the record belongs to.  walk_value: device [n_slots],
+ * the per-walk output of the wost_solve call that wrote the records. */
+int wost_tail_pass(int32_t dim, const wost_records* rec, const float* walk_value, int64_t n_slots,
+                   void* stream);
+/* Workspace bytes for wost_guide_loss_bwd / wost_guide_train_step on `count`
+ * records (per-workgroup partial weight gradients). */
+int64_t wost_guide_train_workspace_bytes(const wost_guide* g, int64_t count);
+/* Per-record loss l_i (device float [count]) with the current parameters
+ * (fp16 shadow). */
+int wost_guide_loss_fwd(const wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
+                        float e_mis, float* loss_out, void* stream);
+/* grad += d/dparams sum_i scale * dloss_i * l_i (dloss device [count] or NULL
+ * for all ones).  grad: device float [P] or NULL for the bound gradient.
+ * Hash-grid activations are recomputed, not stored. */
+int wost_guide_loss_bwd(const wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
+                        float e_mis, float scale, const float* dloss, float* grad, void* workspace,
+                        int64_t ws_bytes, void* stream);
+/* One Adam step (Kingma & Ba) on the master parameters with the bound
+ * gradient, which is then zeroed; refreshes the fp16 shadow. */
+int wost_guide_adam_step(wost_guide* g, const wost_adam* opt, void* stream);
+/* One training step on records [begin, begin + count): mean loss (written to
+ * device float *loss_out if not NULL), gradient, Adam, shadow refresh. */
+int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
+                          const wost_adam* opt, float* loss_out, void* workspace, int64_t ws_bytes,
+                          void* stream);
+
+/* ------------------------------------------------------------ launch tuning
+ * Persistent walk workgroups per compute unit (default 16; 1..64).  Process
+ * wide; affects throughput only, never results. */
+int wost_set_launch(int32_t waves_per_cu);
+/* Traversal-cost instrumentation (process wide).  With a non-NULL device
+ * uint64 [12] array, subsequent wost_solve calls run an instrumented kernel
+ * variant that accumulates, per query type, hierarchy nodes fetched and
+ * primitives tested: [2q] nodes, [2q+1] primitives for q = 0 closest
+ * Dirichlet point, 1 closest silhouette, 2 Neumann sample, 3 Neumann
+ * visibility, 4 source visibility, 5 first hit.  NULL switches it off.
+ * Results are unchanged; only throughput differs. */
+int wost_set_cost_counters(uint64_t* dev_counters12);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WOST_H */

@@ -1,0 +1,557 @@
+// Host-side construction of the walk-on-stars boundary hierarchies
+// (wost_build_bvh) and their upload into caller-owned device memory.
+//
+// Three binary hierarchies are built with object-median splits along the
+// longest centroid extent (depth <= ceil(log2(n / leaf)) + 1, which bounds the
+// traversal stack):
+//   * Dirichlet primitives  -> closest point + epsilon-shell test (Sec. 3.2)
+//   * Neumann primitives    -> first hit inside the star, visibility, and the
+//                              area-weighted Neumann sample (node measures)
+//   * Neumann silhouette candidates (2D vertices, 3D edges) with the inward
+//     normals of their adjacent Neumann primitives and per-node normal cones
+//     -> distance to the closest silhouette, which bounds the star radius
+//     (Sec. 3.2).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "wost_internal.h"
+
+namespace wost {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+namespace {
+
+struct Box {
+    double lo[3] = {INFINITY, INFINITY, INFINITY};
+    double hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    void add(const double* p, int d)
+    {
+        for (int i = 0; i < d; ++i) { lo[i] = std::min(lo[i], p[i]); hi[i] = std::max(hi[i], p[i]); }
+    }
+    void add(const Box& b, int d)
+    {
+        for (int i = 0; i < d; ++i) { lo[i] = std::min(lo[i], b.lo[i]); hi[i] = std::max(hi[i], b.hi[i]); }
+    }
+};
+
+// One item of a hierarchy: its box, centroid, and payload index.
+struct Item {
+    Box box;
+    double c[3];
+    int32_t id;
+};
+
+struct BuiltNode {
+    Box box[2];
+    int32_t c[2] = {-1, -1};
+    int32_t n[2] = {0, 0};
+};
+
+struct Builder {
+    int d;
+    int leaf;
+    bool brute;
+    std::vector<Item>* items;
+    std::vector<BuiltNode> nodes;
+    std::vector<int32_t> order;       // leaf order of item ids
+    int max_depth = 0;
+
+    Box range_box(int b, int e) const
+    {
+        Box bx;
+        for (int i = b; i < e; ++i) bx.add((*items)[i].box, d);
+        return bx;
+    }
+
+    // returns (c, n) describing the subtree over items[b, e)
+    void build(int b, int e, int depth, int32_t& out_c, int32_t& out_n)
+    {
+        max_depth = std::max(max_depth, depth);
+        if (e - b <= leaf || brute) {
+            out_c = (int32_t)order.size();
+            out_n = e - b;
+            for (int i = b; i < e; ++i) order.push_back((*items)[i].id);
+            return;
+        }
+        Box cb;
+        for (int i = b; i < e; ++i) cb.add((*items)[i].c, d);
+        int ax = 0;
+        for (int i = 1; i < d; ++i)
+            if (cb.hi[i] - cb.lo[i] > cb.hi[ax] - cb.lo[ax]) ax = i;
+        int m = (b + e) / 2;
+        std::nth_element(items->begin() + b, items->begin() + m, items->begin() + e,
+                         [ax](const Item& p, const Item& q) {
+                             if (p.c[ax] != q.c[ax]) return p.c[ax] < q.c[ax];
+                             return p.id < q.id;
+                         });
+        int32_t idx = (int32_t)nodes.size();
+        nodes.emplace_back();
+        int32_t c0, n0, c1, n1;
+        build(b, m, depth + 1, c0, n0);
+        build(m, e, depth + 1, c1, n1);
+        BuiltNode& nd = nodes[idx];
+        nd.box[0] = range_box(b, m);
+        nd.box[1] = range_box(m, e);
+        nd.c[0] = c0; nd.n[0] = n0; nd.c[1] = c1; nd.n[1] = n1;
+        out_c = idx;
+        out_n = 0;
+    }
+
+    // Build; guarantees a root node (index 0) exists when there are items.
+    void run()
+    {
+        int n = (int)items->size();
+        if (n == 0) return;
+        int32_t c, k;
+        if (n <= leaf || brute) {
+            nodes.emplace_back();
+            build(0, n, 1, c, k);
+            nodes[0].box[0] = range_box(0, n);
+            nodes[0].c[0] = c; nodes[0].n[0] = k;
+            return;
+        }
+        build(0, n, 0, c, k);
+        // build() placed the root at index 0
+    }
+};
+
+struct Sil {
+    double a[3], b[3];      // 2D: vertex in a (b = a)
+    double n1[3], n2[3];    // inward normals of adjacent Neumann prims; n2 = 0 if boundary
+    bool boundary;
+    int64_t q1, q2;         // adjacent Neumann primitives (caller ids); q2 = -1 if boundary
+};
+
+inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+}  // namespace
+
+}  // namespace wost
+
+using namespace wost;
+
+namespace {
+
+template <class T>
+int64_t push_bytes(std::vector<uint8_t>& img, const T* data, size_t count)
+{
+    size_t off = (img.size() + 255) & ~size_t(255);
+    img.resize(off + sizeof(T) * count);
+    if (count) memcpy(img.data() + off, data, sizeof(T) * count);
+    return (int64_t)off;
+}
+
+// cone of a set of unit vectors: (axis, half-angle); pi if undefined
+void cone_of(const std::vector<std::array<double, 3>>& v, int d, double axis[3], double& half)
+{
+    double s[3] = {0, 0, 0};
+    for (auto& n : v)
+        for (int i = 0; i < d; ++i) s[i] += n[i];
+    double len = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+    if (v.empty() || len < 1e-9 * v.size()) {
+        axis[0] = 1; axis[1] = 0; axis[2] = 0;
+        half = M_PI;
+        return;
+    }
+    for (int i = 0; i < 3; ++i) axis[i] = s[i] / len;
+    double worst = 1.0;
+    for (auto& n : v) worst = std::min(worst, axis[0] * n[0] + axis[1] * n[1] + axis[2] * n[2]);
+    half = std::acos(std::max(-1.0, std::min(1.0, worst)));
+}
+
+}  // namespace
+
+wost::DevGeom wost_geom::devgeom() const
+{
+    DevGeom g{};
+    const uint8_t* base = (const uint8_t*)dev;
+    DevBvh* b[3] = {&g.dir, &g.neu, &g.sil};
+    for (int i = 0; i < 3; ++i) {
+        b[i]->nodes = base + sec[i].nodes;
+        b[i]->prims = (const float4*)(base + sec[i].prims);
+        b[i]->pextra = sec[i].pextra >= 0 ? (const float4*)(base + sec[i].pextra) : nullptr;
+        b[i]->orig = sec[i].orig >= 0 ? (const int32_t*)(base + sec[i].orig) : nullptr;
+        b[i]->n_nodes = sec[i].n_nodes;
+        b[i]->n_prims = sec[i].n_prims;
+    }
+    g.dim = dim;
+    g.diag = (float)diag;
+    g.tau = (float)(1e-6 * diag);
+    for (int i = 0; i < 3; ++i) { g.lo[i] = (float)lo[i]; g.hi[i] = (float)hi[i]; }
+    return g;
+}
+
+extern "C" const char* wost_last_error(void) { return wost::g_err.c_str(); }
+
+extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, const int32_t* prims,
+                              int64_t n_prims, const uint8_t* bc, const wost_build_opts* opts,
+                              wost_geom** out)
+{
+    if (!out) { set_error("wost_build_bvh: out is NULL"); return WOST_EINVAL; }
+    *out = nullptr;
+    if (dim != 2 && dim != 3) { set_error("wost_build_bvh: dim must be 2 or 3 (got %d)", dim); return WOST_EINVAL; }
+    if (!verts || !prims || !bc || n_verts <= 0 || n_prims <= 0) {
+        set_error("wost_build_bvh: empty or NULL geometry");
+        return WOST_EINVAL;
+    }
+    if (n_prims >= (1ll << 30) || n_verts >= (1ll << 31)) {
+        set_error("wost_build_bvh: too many primitives");
+        return WOST_EUNSUPPORTED;
+    }
+    int leaf = 4;
+    bool brute = false;
+    if (opts) {
+        if (opts->leaf_size < 1 || opts->leaf_size > 64) {
+            set_error("wost_build_bvh: leaf_size must be in [1, 64]");
+            return WOST_EINVAL;
+        }
+        leaf = opts->leaf_size;
+        brute = opts->brute_force != 0;
+    }
+    const int d = dim;
+    // ---- per-primitive data in double
+    std::vector<double> P((size_t)n_prims * d * d);
+    std::vector<std::array<double, 3>> nout(n_prims);
+    std::vector<double> meas(n_prims);
+    Box all;
+    for (int64_t v = 0; v < n_verts; ++v) {
+        double p[3] = {0, 0, 0};
+        for (int i = 0; i < d; ++i) {
+            p[i] = verts[v * d + i];
+            if (!std::isfinite(p[i])) { set_error("wost_build_bvh: non-finite vertex %lld", (long long)v); return WOST_EINVAL; }
+        }
+        all.add(p, d);
+    }
+    for (int64_t q = 0; q < n_prims; ++q) {
+        if (bc[q] > 1) { set_error("wost_build_bvh: bc[%lld] must be 0 or 1", (long long)q); return WOST_EINVAL; }
+        for (int k = 0; k < d; ++k) {
+            int32_t vid = prims[q * d + k];
+            if (vid < 0 || vid >= n_verts) {
+                set_error("wost_build_bvh: prim %lld references vertex %d out of range", (long long)q, vid);
+                return WOST_EINVAL;
+            }
+            for (int i = 0; i < d; ++i) P[(q * d + k) * d + i] = verts[(int64_t)vid * d + i];
+        }
+        const double* a = &P[q * d * d];
+        if (d == 2) {
+            double ex = a[2] - a[0], ey = a[3] - a[1];
+            double len = std::sqrt(ex * ex + ey * ey);
+            if (!(len > 0)) { set_error("wost_build_bvh: degenerate segment %lld", (long long)q); return WOST_EINVAL; }
+            nout[q] = {ey / len, -ex / len, 0.0};
+            meas[q] = len;
+        } else {
+            double e1[3], e2[3];
+            for (int i = 0; i < 3; ++i) { e1[i] = a[3 + i] - a[i]; e2[i] = a[6 + i] - a[i]; }
+            double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+            double len = std::sqrt(dot3(c, c));
+            if (!(len > 0)) { set_error("wost_build_bvh: degenerate triangle %lld", (long long)q); return WOST_EINVAL; }
+            nout[q] = {c[0] / len, c[1] / len, c[2] / len};
+            meas[q] = 0.5 * len;
+        }
+    }
+    auto prim_box = [&](int64_t q) {
+        Box b;
+        for (int k = 0; k < d; ++k) b.add(&P[(q * d + k) * d], d);
+        return b;
+    };
+    // ---- silhouette candidates
+    std::vector<Sil> sils;
+    {
+        std::map<std::pair<int64_t, int64_t>, std::vector<int64_t>> adj;
+        for (int64_t q = 0; q < n_prims; ++q) {
+            if (!bc[q]) continue;
+            if (d == 2) {
+                for (int k = 0; k < 2; ++k) adj[{prims[q * 2 + k], -1}].push_back(q);
+            } else {
+                for (int k = 0; k < 3; ++k) {
+                    int64_t a = prims[q * 3 + k], b = prims[q * 3 + (k + 1) % 3];
+                    adj[{std::min(a, b), std::max(a, b)}].push_back(q);
+                }
+            }
+        }
+        sils.reserve(adj.size());
+        for (auto& kv : adj) {
+            Sil s{};
+            int64_t va = kv.first.first, vb = kv.first.second < 0 ? va : kv.first.second;
+            for (int i = 0; i < d; ++i) { s.a[i] = verts[va * d + i]; s.b[i] = verts[vb * d + i]; }
+            const auto& L = kv.second;
+            for (int i = 0; i < 3; ++i) s.n1[i] = -nout[L[0]][i];
+            s.boundary = L.size() < 2;
+            s.q1 = L[0];
+            s.q2 = s.boundary ? -1 : L[1];
+            for (int i = 0; i < 3; ++i) s.n2[i] = s.boundary ? 0.0 : -nout[L[1]][i];
+            sils.push_back(s);
+        }
+    }
+    // ---- hierarchies
+    wost_geom* g = new wost_geom();
+    g->dim = d;
+    for (int i = 0; i < 3; ++i) { g->lo[i] = i < d ? all.lo[i] : 0; g->hi[i] = i < d ? all.hi[i] : 0; }
+    double diag2 = 0;
+    for (int i = 0; i < d; ++i) diag2 += (all.hi[i] - all.lo[i]) * (all.hi[i] - all.lo[i]);
+    g->diag = std::sqrt(diag2);
+    std::vector<uint8_t> img;
+    std::vector<int32_t> orig_all;
+    std::vector<int32_t> neu_internal(n_prims, -1);   // caller id -> internal Neumann id
+    auto int_bits = [](int32_t v) { float f; memcpy(&f, &v, 4); return f; };
+
+    for (int which = 0; which < 3; ++which) {
+        std::vector<Item> items;
+        if (which < 2) {
+            for (int64_t q = 0; q < n_prims; ++q) {
+                if ((int)bc[q] != which) continue;
+                Item it;
+                it.box = prim_box(q);
+                for (int i = 0; i < 3; ++i) it.c[i] = 0.5 * (it.box.lo[i] + it.box.hi[i]);
+                for (int i = d; i < 3; ++i) it.c[i] = 0;
+                it.id = (int32_t)q;
+                items.push_back(it);
+            }
+        } else {
+            for (size_t k = 0; k < sils.size(); ++k) {
+                Item it;
+                it.box.add(sils[k].a, d);
+                it.box.add(sils[k].b, d);
+                for (int i = 0; i < 3; ++i) it.c[i] = i < d ? 0.5 * (it.box.lo[i] + it.box.hi[i]) : 0;
+                it.id = (int32_t)k;
+                items.push_back(it);
+            }
+        }
+        Builder B{d, leaf, brute, &items, {}, {}, 0};
+        B.run();
+        g->max_depth = std::max(g->max_depth, B.max_depth);
+        if (B.max_depth > kMaxDepth) {
+            set_error("wost_build_bvh: hierarchy depth %d exceeds %d", B.max_depth, kMaxDepth);
+            delete g;
+            return WOST_EUNSUPPORTED;
+        }
+        const int nn = (int)B.nodes.size();
+        const int np = (int)B.order.size();
+        // structural validation: every child reference in range, every item in
+        // exactly one leaf (the kernels index without further checks)
+        {
+            std::vector<int> seen(np, 0);
+            bool ok = np == (int)items.size() && (nn > 0 || np == 0);
+            for (int ni = 0; ni < nn && ok; ++ni) {
+                for (int ch = 0; ch < 2 && ok; ++ch) {
+                    const int c = B.nodes[ni].c[ch], n = B.nodes[ni].n[ch];
+                    if (n > 0) {
+                        ok = c >= 0 && c + n <= np;
+                        for (int k = c; ok && k < c + n; ++k) seen[k]++;
+                    } else if (c >= 0) {
+                        ok = c > ni && c < nn;
+                    } else {
+                        ok = ch == 1 && ni == 0;   // only the root's second child may be empty
+                    }
+                }
+            }
+            for (int k = 0; k < np && ok; ++k) ok = seen[k] == 1;
+            if (!ok) {
+                set_error("wost_build_bvh: internal error: hierarchy %d failed validation", which);
+                delete g;
+                return WOST_EINVAL;
+            }
+        }
+        // aggregates per node child: measure (Neumann) or normal cone (silhouettes)
+        std::vector<double> sub_meas(nn * 2, 0.0);
+        std::vector<std::array<double, 4>> sub_cone(nn * 2, {1, 0, 0, M_PI});
+        // iterate nodes in reverse creation order: children are created after parents
+        std::vector<double> node_meas(nn, 0.0);
+        std::vector<std::vector<std::array<double, 3>>> node_normals(which == 2 ? nn : 0);
+        std::vector<char> node_has_boundary(nn, 0);
+        for (int ni = nn - 1; ni >= 0; --ni) {
+            const BuiltNode& nd = B.nodes[ni];
+            for (int ch = 0; ch < 2; ++ch) {
+                double m = 0;
+                std::vector<std::array<double, 3>> normals;
+                bool bnd = false;
+                if (nd.c[ch] < 0 && nd.n[ch] == 0) {
+                    // empty
+                } else if (nd.n[ch] > 0) {
+                    for (int k = nd.c[ch]; k < nd.c[ch] + nd.n[ch]; ++k) {
+                        int32_t id = B.order[k];
+                        if (which == 1) m += meas[id];
+                        if (which == 2) {
+                            const Sil& s = sils[id];
+                            normals.push_back({s.n1[0], s.n1[1], s.n1[2]});
+                            if (!s.boundary) normals.push_back({s.n2[0], s.n2[1], s.n2[2]});
+                            bnd = bnd || s.boundary;
+                        }
+                    }
+                } else {
+                    int c = nd.c[ch];
+                    m = node_meas[c];
+                    if (which == 2) {
+                        normals = node_normals[c];
+                        bnd = node_has_boundary[c];
+                    }
+                }
+                sub_meas[ni * 2 + ch] = m;
+                node_meas[ni] += m;
+                if (which == 2) {
+                    double ax[3], half;
+                    cone_of(normals, d, ax, half);
+                    if (bnd) half = M_PI;
+                    sub_cone[ni * 2 + ch] = {ax[0], ax[1], ax[2], half};
+                    node_normals[ni].insert(node_normals[ni].end(), normals.begin(), normals.end());
+                    node_has_boundary[ni] = node_has_boundary[ni] || bnd;
+                }
+            }
+            if (which == 2) {
+                // keep memory bounded: children's lists are no longer needed
+                for (int ch = 0; ch < 2; ++ch)
+                    if (nd.n[ch] == 0 && nd.c[ch] >= 0) std::vector<std::array<double, 3>>().swap(node_normals[nd.c[ch]]);
+            }
+        }
+        // ---- serialise
+        auto fbox = [](const Box& b, int i, bool hi) { return (float)(hi ? b.hi[i] : b.lo[i]); };
+        auto aux = [&](int ni, int ch) {
+            if (which == 1) return make_float4((float)sub_meas[ni * 2 + ch], 0.f, 0.f, 0.f);
+            if (which == 2) {
+                auto& c = sub_cone[ni * 2 + ch];
+                return make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
+            }
+            return make_float4(0.f, 0.f, 0.f, 0.f);
+        };
+        int64_t off_nodes;
+        if (d == 2) {
+            std::vector<Node2> out(nn);
+            for (int ni = 0; ni < nn; ++ni) {
+                const BuiltNode& nd = B.nodes[ni];
+                Node2& o = out[ni];
+                o.b0 = make_float4(fbox(nd.box[0], 0, 0), fbox(nd.box[0], 1, 0), fbox(nd.box[0], 0, 1), fbox(nd.box[0], 1, 1));
+                o.b1 = make_float4(fbox(nd.box[1], 0, 0), fbox(nd.box[1], 1, 0), fbox(nd.box[1], 0, 1), fbox(nd.box[1], 1, 1));
+                o.ch = make_int4(nd.c[0], nd.n[0], nd.c[1], nd.n[1]);
+                o.aux0 = aux(ni, 0);
+                o.aux1 = aux(ni, 1);
+            }
+            off_nodes = push_bytes(img, out.data(), out.size());
+        } else {
+            std::vector<Node3> out(nn);
+            for (int ni = 0; ni < nn; ++ni) {
+                const BuiltNode& nd = B.nodes[ni];
+                Node3& o = out[ni];
+                const Box &x0 = nd.box[0], &x1 = nd.box[1];
+                o.b0a = make_float4(fbox(x0, 0, 0), fbox(x0, 1, 0), fbox(x0, 2, 0), fbox(x0, 0, 1));
+                o.b0b = make_float4(fbox(x0, 1, 1), fbox(x0, 2, 1), fbox(x1, 0, 0), fbox(x1, 1, 0));
+                o.b1b = make_float4(fbox(x1, 2, 0), fbox(x1, 0, 1), fbox(x1, 1, 1), fbox(x1, 2, 1));
+                o.ch = make_int4(nd.c[0], nd.n[0], nd.c[1], nd.n[1]);
+                o.aux0 = aux(ni, 0);
+                o.aux1 = aux(ni, 1);
+            }
+            off_nodes = push_bytes(img, out.data(), out.size());
+        }
+        std::vector<float4> pr;
+        std::vector<float4> px;
+        std::vector<int32_t> orig;
+        for (int k = 0; k < np; ++k) {
+            int32_t id = B.order[k];
+            if (which < 2) {
+                const double* a = &P[(size_t)id * d * d];
+                if (d == 2) {
+                    pr.push_back(make_float4((float)a[0], (float)a[1], (float)a[2], (float)a[3]));
+                } else {
+                    double e1[3], e2[3];
+                    for (int i = 0; i < 3; ++i) { e1[i] = a[3 + i] - a[i]; e2[i] = a[6 + i] - a[i]; }
+                    pr.push_back(make_float4((float)a[0], (float)a[1], (float)a[2], (float)e1[0]));
+                    pr.push_back(make_float4((float)e1[1], (float)e1[2], (float)e2[0], (float)e2[1]));
+                    pr.push_back(make_float4((float)e2[2], 0.f, 0.f, 0.f));
+                }
+                if (which == 1)
+                    px.push_back(make_float4((float)nout[id][0], (float)nout[id][1], (float)nout[id][2], (float)meas[id]));
+                orig.push_back(id);
+            } else {
+                const Sil& s = sils[id];
+                if (d == 2) {
+                    // adjacent primitives as internal Neumann ids (float bit patterns)
+                    const float f1 = int_bits(neu_internal[s.q1]);
+                    const float f2 = int_bits(s.q2 >= 0 ? neu_internal[s.q2] : -1);
+                    pr.push_back(make_float4((float)s.a[0], (float)s.a[1], (float)s.n1[0], (float)s.n1[1]));
+                    pr.push_back(make_float4((float)s.n2[0], (float)s.n2[1], f1, f2));
+                } else {
+                    const float f1 = int_bits(neu_internal[s.q1]);
+                    const float f2 = int_bits(s.q2 >= 0 ? neu_internal[s.q2] : -1);
+                    pr.push_back(make_float4((float)s.a[0], (float)s.a[1], (float)s.a[2], (float)s.b[0]));
+                    pr.push_back(make_float4((float)s.b[1], (float)s.b[2], (float)s.n1[0], (float)s.n1[1]));
+                    pr.push_back(make_float4((float)s.n1[2], (float)s.n2[0], (float)s.n2[1], (float)s.n2[2]));
+                    pr.push_back(make_float4(f1, f2, 0.f, 0.f));
+                }
+            }
+        }
+        int64_t off_prims = push_bytes(img, pr.data(), pr.size());
+        int64_t off_px = which == 1 ? push_bytes(img, px.data(), px.size()) : -1;
+        int64_t off_orig = which < 2 ? push_bytes(img, orig.data(), orig.size()) : -1;
+        g->sec[which] = {off_nodes, off_prims, off_px, off_orig, nn, np};
+        if (which == 0) g->n_dir = np;
+        if (which == 1) {
+            g->n_neu = np;
+            for (int k = 0; k < np; ++k) neu_internal[B.order[k]] = k;
+        }
+        if (which == 2) g->n_sil = np;
+        if (which < 2) orig_all.insert(orig_all.end(), orig.begin(), orig.end());
+    }
+    img.resize((img.size() + 255) & ~size_t(255));
+    g->bytes = (int64_t)img.size();
+    g->image = (uint8_t*)malloc(img.size());
+    memcpy(g->image, img.data(), img.size());
+    g->orig_host = (int32_t*)malloc(sizeof(int32_t) * (orig_all.size() + 1));
+    memcpy(g->orig_host, orig_all.data(), sizeof(int32_t) * orig_all.size());
+    *out = g;
+    return WOST_OK;
+}
+
+extern "C" int64_t wost_geom_device_bytes(const wost_geom* g) { return g ? g->bytes : -1; }
+
+extern "C" int wost_geom_upload(wost_geom* g, void* dev_buf, int64_t bytes, void* stream)
+{
+    if (!g || !dev_buf) { set_error("wost_geom_upload: NULL argument"); return WOST_EINVAL; }
+    if (bytes < g->bytes) { set_error("wost_geom_upload: buffer has %lld bytes, need %lld", (long long)bytes, (long long)g->bytes); return WOST_ESIZE; }
+    if (((uintptr_t)dev_buf) & 255) { set_error("wost_geom_upload: buffer must be 256-byte aligned"); return WOST_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(dev_buf, g->image, g->bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { set_error("wost_geom_upload: %s", hipGetErrorString(e)); return WOST_EHIP; }
+    g->dev = dev_buf;
+    return WOST_OK;
+}
+
+extern "C" int wost_geom_info(const wost_geom* g, double* o)
+{
+    if (!g || !o) { set_error("wost_geom_info: NULL argument"); return WOST_EINVAL; }
+    o[0] = g->dim; o[1] = (double)g->n_dir; o[2] = (double)g->n_neu; o[3] = (double)g->n_sil;
+    o[4] = g->max_depth; o[5] = g->diag; o[6] = (double)g->bytes; o[7] = 0;
+    return WOST_OK;
+}
+
+extern "C" int64_t wost_geom_prim_index(const wost_geom* g, int32_t internal_id)
+{
+    if (!g || internal_id < 0 || internal_id >= g->n_dir + g->n_neu) return -1;
+    return g->orig_host[internal_id];
+}
+
+extern "C" void wost_geom_free(wost_geom* g)
+{
+    if (!g) return;
+    free(g->image);
+    free(g->orig_host);
+    delete g;
+}

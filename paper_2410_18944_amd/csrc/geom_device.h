@@ -1,0 +1,588 @@
+// Device-side boundary queries of one walk step (gfx950, FP32).
+//
+//  closest_dirichlet  distance / closest point to the Dirichlet boundary
+//                     (epsilon-shell test and terminal value, Sec. 3.2)
+//  closest_silhouette distance to the nearest Neumann silhouette point seen
+//                     from x (bounds the star radius, Sec. 3.2); normal cones
+//                     prune subtrees whose primitives all face x the same way
+//  ray_neumann        first Neumann hit in (tau, tmax): next walk location
+//  visible_neumann    no Neumann primitive crosses the open segment (x, z)
+//  sample_neumann     one area-weighted primitive among those meeting the ball,
+//                     by a single descent with subtree measures as weights
+//
+// Every traversal keeps its stack in LDS: column `lane` of a
+// [kMaxStack][64] array of (node, key) pairs; consecutive lanes hit
+// consecutive banks.
+#pragma once
+
+#include "wost_internal.h"
+
+namespace wost {
+
+struct LdsStack {
+    uint2* base;    // &stack[0][lane]
+    __device__ __forceinline__ void put(int i, int node, float key) const
+    {
+        base[i * kWave] = make_uint2((uint32_t)node, __float_as_uint(key));
+    }
+    __device__ __forceinline__ uint2 get(int i) const { return base[i * kWave]; }
+};
+
+template <int D> struct Box { float lo[D], hi[D]; };
+
+// Traversal cost counters: NoStat compiles to nothing; Stat counts node
+// fetches and primitive tests of one query type.
+struct NoStat {};
+struct Stat {
+    uint32_t nodes = 0, prims = 0;
+};
+__device__ __forceinline__ void stat_node(NoStat*) {}
+__device__ __forceinline__ void stat_prim(NoStat*) {}
+__device__ __forceinline__ void stat_node(Stat* s) { ++s->nodes; }
+__device__ __forceinline__ void stat_prim(Stat* s) { ++s->prims; }
+
+__device__ __forceinline__ void load_node(const Node2* nodes, int i, Box<2>& b0, Box<2>& b1, int4& ch,
+                                          float4& a0, float4& a1)
+{
+    const Node2 n = nodes[i];
+    b0.lo[0] = n.b0.x; b0.lo[1] = n.b0.y; b0.hi[0] = n.b0.z; b0.hi[1] = n.b0.w;
+    b1.lo[0] = n.b1.x; b1.lo[1] = n.b1.y; b1.hi[0] = n.b1.z; b1.hi[1] = n.b1.w;
+    ch = n.ch; a0 = n.aux0; a1 = n.aux1;
+}
+
+__device__ __forceinline__ void load_node(const Node3* nodes, int i, Box<3>& b0, Box<3>& b1, int4& ch,
+                                          float4& a0, float4& a1)
+{
+    const Node3 n = nodes[i];
+    b0.lo[0] = n.b0a.x; b0.lo[1] = n.b0a.y; b0.lo[2] = n.b0a.z;
+    b0.hi[0] = n.b0a.w; b0.hi[1] = n.b0b.x; b0.hi[2] = n.b0b.y;
+    b1.lo[0] = n.b0b.z; b1.lo[1] = n.b0b.w; b1.lo[2] = n.b1b.x;
+    b1.hi[0] = n.b1b.y; b1.hi[1] = n.b1b.z; b1.hi[2] = n.b1b.w;
+    ch = n.ch; a0 = n.aux0; a1 = n.aux1;
+}
+
+// lightweight variant: boxes and children only (aux skipped)
+template <int D>
+__device__ __forceinline__ void load_node_boxes(const typename NodeT<D>::type* nodes, int i, Box<D>& b0,
+                                                Box<D>& b1, int4& ch)
+{
+    float4 a0, a1;
+    load_node(nodes, i, b0, b1, ch, a0, a1);
+}
+
+template <int D>
+__device__ __forceinline__ float box_dist2(const Box<D>& b, const float* x)
+{
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float t = fmaxf(fmaxf(b.lo[i] - x[i], x[i] - b.hi[i]), 0.f);
+        s = fmaf(t, t, s);
+    }
+    return s;
+}
+
+template <int D>
+__device__ __forceinline__ float dot(const float* a, const float* b)
+{
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) s = fmaf(a[i], b[i], s);
+    return s;
+}
+
+// ----------------------------------------------------------------- primitives
+
+// closest point on segment [a, a + e]; returns squared distance
+template <int D>
+__device__ __forceinline__ float closest_seg(const float* x, const float* a, const float* e, float* out)
+{
+    float w[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) w[i] = x[i] - a[i];
+    const float ee = dot<D>(e, e);
+    float t = ee > 0.f ? dot<D>(w, e) / ee : 0.f;
+    t = fminf(fmaxf(t, 0.f), 1.f);
+    float d2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        out[i] = fmaf(t, e[i], a[i]);
+        const float u = x[i] - out[i];
+        d2 = fmaf(u, u, d2);
+    }
+    return d2;
+}
+
+// closest point on triangle (a, a+ab, a+ac) by Voronoi-region classification
+// (Ericson, Real-Time Collision Detection, Sec. 5.1.5); squared distance
+__device__ __forceinline__ float closest_tri(const float* x, const float* a, const float* ab, const float* ac,
+                                             float* out)
+{
+    float ap[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]};
+    const float d1 = dot<3>(ab, ap), d2 = dot<3>(ac, ap);
+    float u = 0.f, v = 0.f;   // out = a + u ab + v ac
+    bool done = false;
+    if (d1 <= 0.f && d2 <= 0.f) { done = true; }
+    float bp[3] = {ap[0] - ab[0], ap[1] - ab[1], ap[2] - ab[2]};
+    const float d3 = dot<3>(ab, bp), d4 = dot<3>(ac, bp);
+    if (!done && d3 >= 0.f && d4 <= d3) { u = 1.f; done = true; }
+    const float vc = d1 * d4 - d3 * d2;
+    if (!done && vc <= 0.f && d1 >= 0.f && d3 <= 0.f) { u = d1 / (d1 - d3); done = true; }
+    float cp[3] = {ap[0] - ac[0], ap[1] - ac[1], ap[2] - ac[2]};
+    const float d5 = dot<3>(ab, cp), d6 = dot<3>(ac, cp);
+    if (!done && d6 >= 0.f && d5 <= d6) { v = 1.f; done = true; }
+    const float vb = d5 * d2 - d1 * d6;
+    if (!done && vb <= 0.f && d2 >= 0.f && d6 <= 0.f) { v = d2 / (d2 - d6); done = true; }
+    const float va = d3 * d6 - d5 * d4;
+    if (!done && va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
+        const float w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        u = 1.f - w; v = w; done = true;
+    }
+    if (!done) {
+        const float den = 1.f / (va + vb + vc);
+        u = vb * den; v = vc * den;
+    }
+    float d2s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        out[i] = a[i] + u * ab[i] + v * ac[i];
+        const float t = x[i] - out[i];
+        d2s = fmaf(t, t, d2s);
+    }
+    return d2s;
+}
+
+template <int D> struct Prim;
+// 2D segment from one float4
+template <> struct Prim<2> {
+    float a[2], e[2];
+    __device__ __forceinline__ void load(const float4* p, int i)
+    {
+        const float4 s = p[i];
+        a[0] = s.x; a[1] = s.y; e[0] = s.z - s.x; e[1] = s.w - s.y;
+    }
+    __device__ __forceinline__ float closest(const float* x, float* out) const { return closest_seg<2>(x, a, e, out); }
+    // ray x + t nu; returns t or +inf
+    __device__ __forceinline__ float ray(const float* x, const float* nu) const
+    {
+        const float den = nu[0] * e[1] - nu[1] * e[0];
+        const float wx = a[0] - x[0], wy = a[1] - x[1];
+        const float t = (wx * e[1] - wy * e[0]) / den;
+        const float u = (wx * nu[1] - wy * nu[0]) / den;
+        return (den != 0.f && u >= 0.f && u <= 1.f) ? t : INFINITY;
+    }
+    __device__ __forceinline__ void point(float s, float, float* z) const
+    {
+        z[0] = fmaf(s, e[0], a[0]);
+        z[1] = fmaf(s, e[1], a[1]);
+    }
+};
+// 3D triangle from three float4
+template <> struct Prim<3> {
+    float a[3], e1[3], e2[3];
+    __device__ __forceinline__ void load(const float4* p, int i)
+    {
+        const float4 s0 = p[3 * i], s1 = p[3 * i + 1], s2 = p[3 * i + 2];
+        a[0] = s0.x; a[1] = s0.y; a[2] = s0.z;
+        e1[0] = s0.w; e1[1] = s1.x; e1[2] = s1.y;
+        e2[0] = s1.z; e2[1] = s1.w; e2[2] = s2.x;
+    }
+    __device__ __forceinline__ float closest(const float* x, float* out) const { return closest_tri(x, a, e1, e2, out); }
+    // Moller-Trumbore
+    __device__ __forceinline__ float ray(const float* x, const float* nu) const
+    {
+        const float p[3] = {nu[1] * e2[2] - nu[2] * e2[1], nu[2] * e2[0] - nu[0] * e2[2], nu[0] * e2[1] - nu[1] * e2[0]};
+        const float det = dot<3>(e1, p);
+        const float inv = 1.f / det;
+        const float tv[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]};
+        const float u = dot<3>(tv, p) * inv;
+        const float q[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2], tv[0] * e1[1] - tv[1] * e1[0]};
+        const float v = dot<3>(nu, q) * inv;
+        const float t = dot<3>(e2, q) * inv;
+        return (det != 0.f && u >= 0.f && v >= 0.f && u + v <= 1.f) ? t : INFINITY;
+    }
+    // uniform point on the triangle from two uniforms
+    __device__ __forceinline__ void point(float s1, float s2, float* z) const
+    {
+        const float sq = sqrtf(s1);
+        const float b = sq * (1.f - s2), c = sq * s2;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) z[i] = a[i] + b * e1[i] + c * e2[i];
+    }
+};
+
+// ----------------------------------------------------------------- closest point
+
+// Returns the squared distance (< best2 on entry to count as found) and the
+// closest point; prim_out = internal primitive id or -1.
+template <int D, class S = NoStat>
+__device__ float closest_dirichlet(const DevBvh& b, const float* x, float best2, float* xbar, int* prim_out,
+                                   const LdsStack& st, S* s = nullptr)
+{
+    using NodeType = typename NodeT<D>::type;
+    const NodeType* nodes = (const NodeType*)b.nodes;
+    int bp = -1;
+    if (b.n_nodes == 0) { *prim_out = -1; return best2; }
+    int sp = 0, node = 0;
+    for (;;) {
+        Box<D> b0, b1;
+        int4 ch;
+        load_node_boxes<D>(nodes, node, b0, b1, ch);
+        stat_node(s);
+        float d0 = box_dist2<D>(b0, x), d1 = box_dist2<D>(b1, x);
+        bool v0 = d0 < best2, v1 = d1 < best2;
+        if (v0 && ch.y > 0) {
+            for (int k = ch.x; k < ch.x + ch.y; ++k) {
+                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+                float c[D];
+                const float dd = pr.closest(x, c);
+                if (dd < best2) {
+                    best2 = dd; bp = k;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) xbar[i] = c[i];
+                }
+            }
+            v0 = false;
+        }
+        if (v1 && ch.w > 0) {
+            for (int k = ch.z; k < ch.z + ch.w; ++k) {
+                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+                float c[D];
+                const float dd = pr.closest(x, c);
+                if (dd < best2) {
+                    best2 = dd; bp = k;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) xbar[i] = c[i];
+                }
+            }
+            v1 = false;
+        }
+        v0 = v0 && d0 < best2;
+        v1 = v1 && d1 < best2;
+        if (v0 && v1) {
+            const bool first0 = d0 <= d1;
+            st.put(sp++, first0 ? ch.z : ch.x, first0 ? d1 : d0);
+            node = first0 ? ch.x : ch.z;
+            continue;
+        }
+        if (v0) { node = ch.x; continue; }
+        if (v1) { node = ch.z; continue; }
+        bool found = false;
+        while (sp > 0) {
+            const uint2 e = st.get(--sp);
+            if (__uint_as_float(e.y) < best2) { node = (int)e.x; found = true; break; }
+        }
+        if (!found) break;
+    }
+    *prim_out = bp;
+    return best2;
+}
+
+// ----------------------------------------------------------------- silhouettes
+
+// true if the normal cone (axis, half-angle) of a child cannot contain a
+// silhouette as seen from x: every primitive normal inside the cone makes an
+// angle below pi/2 (all front) or above pi/2 (all back) with x - p for every
+// p in the box.
+template <int D>
+__device__ __forceinline__ bool cone_culls(const Box<D>& b, const float4& cone, const float* x)
+{
+    if (cone.w >= 1.5707963f) return false;
+    float c[D], v[D], R2 = 0.f, dist2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        c[i] = 0.5f * (b.lo[i] + b.hi[i]);
+        const float h = 0.5f * (b.hi[i] - b.lo[i]);
+        R2 = fmaf(h, h, R2);
+        v[i] = x[i] - c[i];
+        dist2 = fmaf(v[i], v[i], dist2);
+    }
+    if (dist2 <= R2 * 1.0001f + 1e-30f) return false;
+    const float dist = sqrtf(dist2);
+    const float phi = asinf(fminf(sqrtf(R2) / dist, 1.f));
+    const float ax[3] = {cone.x, cone.y, cone.z};
+    const float cb = fminf(fmaxf(dot<D>(v, ax) / dist, -1.f), 1.f);
+    const float beta = acosf(cb);
+    const float margin = 1e-3f;
+    const float spread = cone.w + phi + margin;
+    return (beta + spread < 1.5707963f) || (beta - spread > 1.5707963f);
+}
+
+// Silhouette candidate k seen from x.  A Neumann primitive faces x from the
+// front if x lies on its domain side; the primitive the walker stands on
+// (internal id `onp`) is front by definition, every other facing decision is
+// the exact sign.  Returns the squared distance if the candidate is a
+// silhouette (adjacent primitives facing differently, or a boundary feature
+// with a single adjacent Neumann primitive), +inf otherwise.
+template <int D>
+__device__ __forceinline__ float sil_prim_dist2(const float4* p, int k, const float* x, int onp)
+{
+    float a[D], n1[D], n2[D], e[D];
+    int q1, q2;
+    if (D == 2) {
+        const float4 s0 = p[2 * k], s1 = p[2 * k + 1];
+        a[0] = s0.x; a[1] = s0.y; n1[0] = s0.z; n1[1] = s0.w;
+        n2[0] = s1.x; n2[1] = s1.y;
+        q1 = __float_as_int(s1.z); q2 = __float_as_int(s1.w);
+    } else {
+        const float4 s0 = p[4 * k], s1 = p[4 * k + 1], s2 = p[4 * k + 2], s3 = p[4 * k + 3];
+        a[0] = s0.x; a[1] = s0.y; a[2] = s0.z;
+        e[0] = s0.w - s0.x; e[1] = s1.x - s0.y; e[2] = s1.y - s0.z;
+        n1[0] = s1.z; n1[1] = s1.w; n1[2] = s2.x;
+        n2[0] = s2.y; n2[1] = s2.z; n2[2] = s2.w;
+        q1 = __float_as_int(s3.x); q2 = __float_as_int(s3.y);
+    }
+    float w[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) w[i] = x[i] - a[i];
+    if (q2 >= 0) {
+        const bool f1 = q1 == onp || dot<D>(w, n1) >= 0.f;
+        const bool f2 = q2 == onp || dot<D>(w, n2) >= 0.f;
+        if (f1 == f2) return INFINITY;
+    }
+    if (D == 2) return dot<D>(w, w);
+    float c[D];
+    return closest_seg<D>(x, a, e, c);
+}
+
+template <int D, class S = NoStat>
+__device__ float closest_silhouette(const DevBvh& b, const float* x, float best2, int onp, const LdsStack& st,
+                                    S* s = nullptr)
+{
+    using NodeType = typename NodeT<D>::type;
+    const NodeType* nodes = (const NodeType*)b.nodes;
+    if (b.n_nodes == 0) return best2;
+    int sp = 0, node = 0;
+    for (;;) {
+        Box<D> b0, b1;
+        int4 ch;
+        float4 c0, c1;
+        load_node(nodes, node, b0, b1, ch, c0, c1);
+        stat_node(s);
+        float d0 = box_dist2<D>(b0, x), d1 = box_dist2<D>(b1, x);
+        bool v0 = d0 < best2 && !cone_culls<D>(b0, c0, x);
+        bool v1 = d1 < best2 && !cone_culls<D>(b1, c1, x);
+        if (v0 && ch.y > 0) {
+            for (int k = ch.x; k < ch.x + ch.y; ++k) best2 = fminf(best2, sil_prim_dist2<D>(b.prims, k, x, onp)), stat_prim(s);
+            v0 = false;
+        }
+        if (v1 && ch.w > 0) {
+            for (int k = ch.z; k < ch.z + ch.w; ++k) best2 = fminf(best2, sil_prim_dist2<D>(b.prims, k, x, onp)), stat_prim(s);
+            v1 = false;
+        }
+        v0 = v0 && d0 < best2;
+        v1 = v1 && d1 < best2;
+        if (v0 && v1) {
+            const bool first0 = d0 <= d1;
+            st.put(sp++, first0 ? ch.z : ch.x, first0 ? d1 : d0);
+            node = first0 ? ch.x : ch.z;
+            continue;
+        }
+        if (v0) { node = ch.x; continue; }
+        if (v1) { node = ch.z; continue; }
+        bool found = false;
+        while (sp > 0) {
+            const uint2 e = st.get(--sp);
+            if (__uint_as_float(e.y) < best2) { node = (int)e.x; found = true; break; }
+        }
+        if (!found) break;
+    }
+    return best2;
+}
+
+// ----------------------------------------------------------------- rays
+
+// slab test: entry distance of the ray into the box within [tmin, tmax], or +inf
+template <int D>
+__device__ __forceinline__ float ray_box(const Box<D>& b, const float* x, const float* inv, float tmin, float tmax)
+{
+    float t0 = tmin, t1 = tmax;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const float a = (b.lo[i] - x[i]) * inv[i];
+        const float c = (b.hi[i] - x[i]) * inv[i];
+        t0 = fmaxf(t0, fminf(a, c));
+        t1 = fminf(t1, fmaxf(a, c));
+    }
+    return t0 <= t1 ? t0 : INFINITY;
+}
+
+// first Neumann hit with t in (tau, tmax), skipping internal primitive `skip`;
+// returns t (or +inf) and the hit primitive (or -1).  Walk rays pass tau = 0:
+// a walker standing on the boundary shoots from an origin offset along its
+// normal instead, so no genuine crossing near the origin is ever ignored.
+template <int D, class S = NoStat>
+__device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, float tmax, float tau, int skip,
+                             int* hit, const LdsStack& st, S* s = nullptr)
+{
+    using NodeType = typename NodeT<D>::type;
+    const NodeType* nodes = (const NodeType*)b.nodes;
+    *hit = -1;
+    if (b.n_nodes == 0) return INFINITY;
+    float inv[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) inv[i] = 1.f / nu[i];
+    float best = tmax;
+    int sp = 0, node = 0;
+    for (;;) {
+        Box<D> b0, b1;
+        int4 ch;
+        load_node_boxes<D>(nodes, node, b0, b1, ch);
+        stat_node(s);
+        const float e0 = ch.x >= 0 ? ray_box<D>(b0, x, inv, 0.f, best) : INFINITY;
+        const float e1 = ch.z >= 0 ? ray_box<D>(b1, x, inv, 0.f, best) : INFINITY;
+        bool v0 = e0 < INFINITY, v1 = e1 < INFINITY;
+        if (v0 && ch.y > 0) {
+            for (int k = ch.x; k < ch.x + ch.y; ++k) {
+                if (k == skip) continue;
+                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+                const float t = pr.ray(x, nu);
+                if (t > tau && t < best) { best = t; *hit = k; }
+            }
+            v0 = false;
+        }
+        if (v1 && ch.w > 0) {
+            for (int k = ch.z; k < ch.z + ch.w; ++k) {
+                if (k == skip) continue;
+                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+                const float t = pr.ray(x, nu);
+                if (t > tau && t < best) { best = t; *hit = k; }
+            }
+            v1 = false;
+        }
+        v0 = v0 && e0 < best;
+        v1 = v1 && e1 < best;
+        if (v0 && v1) {
+            const bool first0 = e0 <= e1;
+            st.put(sp++, first0 ? ch.z : ch.x, first0 ? e1 : e0);
+            node = first0 ? ch.x : ch.z;
+            continue;
+        }
+        if (v0) { node = ch.x; continue; }
+        if (v1) { node = ch.z; continue; }
+        bool found = false;
+        while (sp > 0) {
+            const uint2 e = st.get(--sp);
+            if (__uint_as_float(e.y) < best) { node = (int)e.x; found = true; break; }
+        }
+        if (!found) break;
+    }
+    return *hit >= 0 ? best : INFINITY;
+}
+
+// no Neumann primitive other than `skip` crosses the ray x + t nu (unit nu)
+// at a parameter t in (t_lo, t_hi)
+template <int D, class S = NoStat>
+__device__ bool visible_neumann(const DevBvh& b, const float* x, const float* nu, float t_lo, float t_hi, int skip,
+                                const LdsStack& st, S* s = nullptr)
+{
+    using NodeType = typename NodeT<D>::type;
+    const NodeType* nodes = (const NodeType*)b.nodes;
+    if (b.n_nodes == 0) return true;
+    float inv[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) inv[i] = 1.f / nu[i];
+    const float tmax = t_hi;
+    const float tau = t_lo;
+    int sp = 0, node = 0;
+    for (;;) {
+        Box<D> b0, b1;
+        int4 ch;
+        load_node_boxes<D>(nodes, node, b0, b1, ch);
+        stat_node(s);
+        bool v0 = ch.x >= 0 && ray_box<D>(b0, x, inv, 0.f, tmax) < INFINITY;
+        bool v1 = ch.z >= 0 && ray_box<D>(b1, x, inv, 0.f, tmax) < INFINITY;
+        if (v0 && ch.y > 0) {
+            for (int k = ch.x; k < ch.x + ch.y; ++k) {
+                if (k == skip) continue;
+                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+                const float t = pr.ray(x, nu);
+                if (t > tau && t < tmax) return false;
+            }
+            v0 = false;
+        }
+        if (v1 && ch.w > 0) {
+            for (int k = ch.z; k < ch.z + ch.w; ++k) {
+                if (k == skip) continue;
+                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+                const float t = pr.ray(x, nu);
+                if (t > tau && t < tmax) return false;
+            }
+            v1 = false;
+        }
+        if (v0 && v1) { st.put(sp++, ch.z, 0.f); node = ch.x; continue; }
+        if (v0) { node = ch.x; continue; }
+        if (v1) { node = ch.z; continue; }
+        if (sp == 0) break;
+        node = (int)st.get(--sp).x;
+    }
+    return true;
+}
+
+// ----------------------------------------------------------------- Neumann sample
+
+// Pick one Neumann primitive meeting the ball B(x, r): descend choosing each
+// child with probability proportional to its subtree measure (children whose
+// box misses the ball get weight 0), then a primitive of the leaf in
+// proportion to its measure among the leaf primitives meeting the ball.
+// Returns the primitive (or -1) and the probability of having chosen it.
+template <int D, class S = NoStat>
+__device__ int sample_neumann(const DevBvh& b, const float* x, float r, float u, float* prob, S* s = nullptr)
+{
+    using NodeType = typename NodeT<D>::type;
+    const NodeType* nodes = (const NodeType*)b.nodes;
+    *prob = 0.f;
+    if (b.n_nodes == 0) return -1;
+    const float r2 = r * r;
+    float P = 1.f;
+    int node = 0;
+    for (;;) {
+        Box<D> b0, b1;
+        int4 ch;
+        float4 a0, a1;
+        load_node(nodes, node, b0, b1, ch, a0, a1);
+        stat_node(s);
+        const float w0 = box_dist2<D>(b0, x) < r2 ? a0.x : 0.f;
+        const float w1 = box_dist2<D>(b1, x) < r2 ? a1.x : 0.f;
+        const float W = w0 + w1;
+        if (!(W > 0.f)) return -1;
+        const float p0 = w0 / W;
+        int c, n;
+        if (u < p0) {
+            c = ch.x; n = ch.y; P *= p0;
+            u = u / p0;
+        } else {
+            c = ch.z; n = ch.w; P *= (1.f - p0);
+            u = (u - p0) / (1.f - p0);
+        }
+        u = fminf(fmaxf(u, 0.f), 0.99999994f);
+        if (n > 0) {
+            // leaf: measure-weighted choice among primitives meeting the ball
+            float tot = 0.f;
+            for (int k = c; k < c + n; ++k) {
+                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+                float z[D];
+                if (pr.closest(x, z) < r2) tot += b.pextra[k].w;
+            }
+            if (!(tot > 0.f)) return -1;
+            const float target = u * tot;
+            float acc = 0.f;
+            int sel = -1;
+            float wsel = 0.f;
+            for (int k = c; k < c + n; ++k) {
+                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+                float z[D];
+                if (!(pr.closest(x, z) < r2)) continue;
+                const float w = b.pextra[k].w;
+                sel = k; wsel = w;
+                acc += w;
+                if (target < acc) break;
+            }
+            *prob = P * (wsel / tot);
+            return sel;
+        }
+        node = c;
+    }
+}
+
+}  // namespace wost

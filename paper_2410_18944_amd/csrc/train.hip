@@ -1,0 +1,673 @@
+// Online training of the guide (Sec. 4.2 KL objective, Sec. 4.4 selection
+// probability loss, Sec. 5.2 online scheme) on gfx950.
+//
+// Per training record (x, nu, n, p_sample, p_t) the loss
+//     l = -w [ log p_g(nu | Theta(x)) + e log( c sg(p_g) + (1 - c) p_u ) ],
+//     w = p_t / p_sample,
+// has exactly the paper's one-sample gradients: d l / d Theta is the
+// "one_sample_kld" estimator -p_t grad p_g / (p~ p_g), and d l / d c is the
+// "one_sample_sp" estimator -e p_t (p_g - p_u) / p~^2 (sg = stop-gradient).
+//
+// Kernel layout: one 64-wide wave per workgroup processes tiles of 64
+// records.  Forward recomputes the grid encoding and runs the MLP on MFMA in
+// the transposed form (see guide_device.h), storing every layer's input
+// activations in LDS as [feature][walk] fp16.  The per-record output gradient
+// is scaled by a power of two (per tile and per layer) before the fp16
+// conversion.  Backward propagates dH = W dZ in registers with pre-swizzled
+// W fragments; weight gradients dW^T = sum_walk dZ^T H contract over the tile
+// from the LDS operands and accumulate in an fp32 LDS copy per workgroup,
+// written once as a partial and reduced deterministically.  Grid gradients are
+// scattered with fp32 atomics into the corners the forward pass read.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "guide_device.h"
+#include "guide_internal.h"
+#include "walk_common.h"
+
+namespace wost {
+
+struct TrainArgs {
+    const float* rec;
+    int64_t cap;
+    int64_t begin, count;
+    float e_mis;
+    float scale;            // multiplies every record's gradient
+    const float* dloss;     // per-record upstream gradient (or null = 1)
+    float* loss_out;        // per-record loss (or null)
+    float* loss_sum;        // device scalar += loss_scale * sum(loss) (or null)
+    float loss_scale;
+    float* grad;            // gradient vector (grid part first)
+    float* partials;        // [gridDim.x][p_mlp]
+    int32_t backward;
+    int32_t p_mlp;
+    int32_t off[kMaxLayers];   // layer weight offsets relative to the MLP start
+    int32_t in[kMaxLayers];
+    int32_t out[kMaxLayers];
+};
+
+// B(k) = d log v / d kappa + (1 - mu.nu): the kappa derivative of the vMF
+// log-density is mu.nu - 1 + B(k), a small difference of O(1) terms near the
+// mode, so B is computed without cancellation.
+//  2D: B = 1 - I1(k)/I0(k).  For k >= 20 the asymptotic series of the ratio
+//      (from r' = 1 - r/k - r^2, r = I1/I0): 1/(2k) + 1/(8k^2) + 1/(8k^3)
+//      + 25/(128k^4) + 13/(32k^5) + 1073/(1024k^6); below, the polynomial
+//      approximations of I0e and I1e.
+//  3D: B = 1 + 1/k - coth(k) = 1/k - 2/(e^{2k} - 1) (series for small k).
+__device__ __forceinline__ float vmf_dlog_offset2(float k)
+{
+    if (k >= 20.f) {
+        const float u = 1.f / k;
+        return u * (0.5f + u * (0.125f + u * (0.125f + u * (25.f / 128.f + u * (13.f / 32.f + u * (1073.f / 1024.f))))));
+    }
+    return 1.f - i1e_f(k) / i0e_f(k);
+}
+
+__device__ __forceinline__ float vmf_dlog_offset3(float k)
+{
+    if (k < 0.3f) {
+        const float k2 = k * k;
+        return 1.f + k * (-1.f / 3.f + k2 * (1.f / 45.f - k2 * (2.f / 945.f)));
+    }
+    return 1.f / k - 2.f / expm1f(2.f * k);
+}
+
+__device__ __forceinline__ float softplus(float z) { return fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))); }
+
+// Loss of one record and (optionally, in place) its gradient w.r.t. the raw
+// outputs y (row in LDS; padded entries untouched).  dscale multiplies dy.
+template <int D>
+__device__ float record_loss_grad(float* y, int K, const float* nu, const float* n, bool onN, float ps, float pt,
+                                  float e, bool want_grad, float dscale)
+{
+    const float area = D == 2 ? 2.f * kPi : 4.f * kPi;
+    float nr[D];
+    {
+        const float cn = dot<D>(nu, n);
+#pragma unroll
+        for (int i = 0; i < D; ++i) nr[i] = fmaf(-2.f * cn, n[i], nu[i]);
+    }
+    // pass 1: log-softmax of lambda', mixture log-density (streaming LSE)
+    float lmax = -INFINITY;
+    for (int i = 0; i < K; ++i) lmax = fmaxf(lmax, y[i * (D + 2) + D + 1]);
+    float lsum = 0.f;
+    for (int i = 0; i < K; ++i) lsum += expf(y[i * (D + 2) + D + 1] - lmax);
+    const float lse_lam = lmax + logf(lsum);
+    float m = -INFINITY, s = 0.f;
+    for (int i = 0; i < K; ++i) {
+        const float* r = y + i * (D + 2);
+        float n2 = 0.f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) n2 = fmaf(r[d], r[d], n2);
+        const float inv = rsqrtf(fmaxf(n2, 1e-30f));
+        float mu[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) mu[d] = r[d] * inv;
+        const float k = expf(fminf(fmaxf(r[D], kKappaLogMin), kKappaLogMax));
+        const float base = r[D + 1] - lse_lam + vmf_lognorm<D>(k);
+        const float t1 = fmaf(k, dot<D>(mu, nu) - 1.f, base);
+        float mt = fmaxf(m, t1);
+        s = s * expf(m - mt) + expf(t1 - mt);
+        m = mt;
+        if (onN) {
+            const float t2 = fmaf(k, dot<D>(mu, nr) - 1.f, base);
+            mt = fmaxf(m, t2);
+            s = s * expf(m - mt) + expf(t2 - mt);
+            m = mt;
+        }
+    }
+    const float log_pg = m + logf(s);
+    // selection probability c = sigmoid(c'), c' clamped to [-15, 15]; the MIS
+    // pdf c p_g + (1 - c) p_u is combined in log space
+    const float craw = y[K * (D + 2)];
+    const float cr = fminf(fmaxf(craw, -kCLogit), kCLogit);
+    const float log_c = -softplus(-cr), log_1mc = -softplus(cr);
+    const float c = expf(log_c);
+    const float log_pu = logf((onN ? 2.f : 1.f) / area);
+    const float la = log_c + log_pg, lb = log_1mc + log_pu;
+    const float lmx = fmaxf(la, lb);
+    const float log_pm = lmx + logf(expf(la - lmx) + expf(lb - lmx));
+    const float w = ps > 0.f ? pt / ps : 0.f;
+    const float loss = -w * (log_pg + e * log_pm);
+    if (!want_grad) return loss;
+    const float gw = -w * dscale;
+    // pass 2: responsibilities and gradients, lobe by lobe (reads lobe i
+    // before overwriting it)
+    for (int i = 0; i < K; ++i) {
+        float* r = y + i * (D + 2);
+        float n2 = 0.f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) n2 = fmaf(r[d], r[d], n2);
+        const float inv = rsqrtf(fmaxf(n2, 1e-30f));
+        float mu[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) mu[d] = r[d] * inv;
+        const float kp = r[D];
+        const bool clamped = kp < kKappaLogMin || kp > kKappaLogMax;
+        const float k = expf(fminf(fmaxf(kp, kKappaLogMin), kKappaLogMax));
+        const float lam = expf(r[D + 1] - lse_lam);
+        const float base = r[D + 1] - lse_lam + vmf_lognorm<D>(k);
+        const float B = D == 2 ? vmf_dlog_offset2(k) : vmf_dlog_offset3(k);
+        const float c1 = dot<D>(mu, nu);
+        const float g1 = expf(fmaf(k, c1 - 1.f, base) - log_pg);
+        float c2 = 0.f, g2 = 0.f;
+        if (onN) {
+            c2 = dot<D>(mu, nr);
+            g2 = expf(fmaf(k, c2 - 1.f, base) - log_pg);
+        }
+        // d log p_g / d lambda'_i, kappa'_i, mu'_i
+        const float dlam = g1 + g2 - lam;
+        const float dkap = clamped ? 0.f : k * (g1 * (B - (1.f - c1)) + g2 * (B - (1.f - c2)));
+        float dmu[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            float v = g1 * (nu[d] - c1 * mu[d]);
+            if (onN) v += g2 * (nr[d] - c2 * mu[d]);
+            dmu[d] = v * k * inv;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) r[d] = gw * dmu[d];
+        r[D] = gw * dkap;
+        r[D + 1] = gw * dlam;
+    }
+    // d log(c p_g + (1 - c) p_u) / d c' = r_g - c, r_g = c p_g / p~
+    const bool c_clamped = craw < -kCLogit || craw > kCLogit;
+    y[K * (D + 2)] = c_clamped ? 0.f : gw * e * (expf(la - log_pm) - c);
+    return loss;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// power-of-two factor bringing max |v| to about 2^10 (1 if max is 0)
+__device__ __forceinline__ float pow2_scale(float maxabs)
+{
+    if (!(maxabs > 0.f) || !(maxabs < INFINITY)) return 1.f;
+    return exp2f(floorf(log2f(1024.f / maxabs)));
+}
+
+__device__ __forceinline__ half4_t lds_h4(const _Float16* p)
+{
+    return *(const half4_t*)p;
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const TrainArgs a)
+{
+    extern __shared__ float smem[];
+    const int lane = threadIdx.x, g4 = lane >> 4, col = lane & 15;
+    const int L = g.n_layers;
+    const int K = g.K;
+    const int out_pad = g.out_pad;
+    const int ystride = out_pad + 1;
+    const int kb0 = g.kb[0];
+    const int rows_act = 16 * kb0 + 64 * (L - 1);
+    const int rmax = out_pad > 64 ? out_pad : 64;
+    float* s_dw = smem;
+    float* s_y = smem + (a.backward ? a.p_mlp : 0);
+    _Float16* s_act = (_Float16*)(s_y + 64 * ystride);
+    _Float16* s_d0 = s_act + rows_act * 64;
+    _Float16* s_d1 = s_d0 + rmax * 64;
+    const int64_t T = 1ll << g.log2T;
+
+    if (a.backward)
+        for (int j = lane; j < a.p_mlp; j += 64) s_dw[j] = 0.f;
+    __syncthreads();
+
+    const int64_t n_tiles = (a.count + 63) / 64;
+    float loss_acc = 0.f;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t i = tile * 64 + lane;
+        const bool valid = i < a.count;
+        const int64_t r = a.begin + i;
+        float x[D], nu[D], nn[D];
+        float ps = 1.f, pt = 0.f;
+        bool onN = false;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            x[d] = valid ? a.rec[(int64_t)d * a.cap + r] : 0.f;
+            nu[d] = valid ? a.rec[(int64_t)(D + d) * a.cap + r] : 1.f / (float)D;
+            nn[d] = valid ? a.rec[(int64_t)(2 * D + d) * a.cap + r] : 0.f;
+            onN = onN || nn[d] != 0.f;
+        }
+        if (valid) {
+            ps = a.rec[(int64_t)(3 * D) * a.cap + r];
+            pt = a.rec[(int64_t)(3 * D + 4) * a.cap + r];
+        }
+        // ---------------- forward
+        for (int cb = 0; cb < 4; ++cb) {
+            const int w = 16 * cb + col;
+            float xw[D], xh[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) xw[d] = __shfl(x[d], w);
+            normalise_input<D>(g, xw, xh);
+            half4_t act[4];
+            for (int kb = 0; kb < kb0; ++kb) {
+                const int l0 = 8 * kb + 2 * g4;
+                const float2 f0 = grid_level<D>(g, l0, xh);
+                const float2 f1 = grid_level<D>(g, l0 + 1, xh);
+                half4_t h;
+                h[0] = (_Float16)f0.x; h[1] = (_Float16)f0.y; h[2] = (_Float16)f1.x; h[3] = (_Float16)f1.y;
+                act[kb] = h;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s_act[(16 * kb + 4 * g4 + e) * 64 + w] = h[e];
+            }
+            int row_off = 16 * kb0;
+            for (int layer = 0; layer + 1 < L; ++layer) {
+                const half4_t* A = g.frags + g.frag_off[layer];
+                const int KB = g.kb[layer];
+                half4_t nxt[4];
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb) {
+                    float4_t c = {0.f, 0.f, 0.f, 0.f};
+                    for (int kb = 0; kb < KB; ++kb)
+                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
+                    half4_t h;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) h[e] = (_Float16)fmaxf(c[e], 0.f);
+                    nxt[mb] = h;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) s_act[(row_off + 16 * mb + 4 * g4 + e) * 64 + w] = h[e];
+                }
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb) act[mb] = nxt[mb];
+                row_off += 64;
+            }
+            {
+                const int layer = L - 1;
+                const half4_t* A = g.frags + g.frag_off[layer];
+                const int KB = g.kb[layer];
+                for (int mb = 0; mb < g.mb[layer]; ++mb) {
+                    float4_t c = {0.f, 0.f, 0.f, 0.f};
+                    for (int kb = 0; kb < KB; ++kb)
+                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) s_y[w * ystride + 16 * mb + 4 * g4 + e] = c[e];
+                }
+            }
+        }
+        __syncthreads();
+        // ---------------- per-record loss and output gradient (lane = record)
+        float* yrow = s_y + lane * ystride;
+        const float up = valid ? (a.dloss ? a.dloss[i] : 1.f) * a.scale : 0.f;
+        const float loss = record_loss_grad<D>(yrow, K, nu, nn, onN, ps, pt, a.e_mis, a.backward != 0, up);
+        if (valid) {
+            if (a.loss_out) a.loss_out[i] = loss;
+            loss_acc += loss;
+        }
+        if (!a.backward) {
+            __syncthreads();
+            continue;
+        }
+        // padded records and any non-finite gradient contribute exactly zero
+        for (int j = 0; j < out_pad; ++j)
+            if (!valid || j >= g.n_out || !(fabsf(yrow[j]) < INFINITY)) yrow[j] = 0.f;
+        float mx = 0.f;
+        for (int j = 0; j < out_pad; ++j) mx = fmaxf(mx, fabsf(yrow[j]));
+        float Sc = pow2_scale(wave_max(mx));
+        for (int j = 0; j < out_pad; ++j) s_d0[j * 64 + lane] = (_Float16)(yrow[j] * Sc);
+        __syncthreads();
+        // ---------------- backward
+        _Float16* cur = s_d0;
+        _Float16* nxt = s_d1;
+        for (int layer = L - 1; layer >= 0; --layer) {
+            const int rows_out = layer == L - 1 ? out_pad : 64;
+            const int rows_in = layer == 0 ? 16 * kb0 : 64;
+            const _Float16* act = s_act + (layer == 0 ? 0 : (16 * kb0 + 64 * (layer - 1))) * 64;
+            const int outr = a.out[layer];
+            const float inv_sc = 1.f / Sc;
+            // weight gradient: dW^T[out][in] += sum_walk dZ^T[out][walk] H[walk][in]
+            for (int mb = 0; mb < rows_out / 16; ++mb) {
+                for (int nb = 0; nb < rows_in / 16; ++nb) {
+                    float4_t c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const half4_t Av = lds_h4(cur + (16 * mb + col) * 64 + 16 * kk + 4 * g4);
+                        const half4_t Bv = lds_h4(act + (16 * nb + col) * 64 + 16 * kk + 4 * g4);
+                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(Av, Bv, c, 0, 0, 0);
+                    }
+                    const int in_i = 16 * nb + col;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int o = 16 * mb + 4 * g4 + e;
+                        if (o < outr) s_dw[a.off[layer] + in_i * outr + o] += c[e] * inv_sc;
+                    }
+                }
+            }
+            // data gradient dH^T = W dZ^T (rows = input features of this layer)
+            const half4_t* Bw = g.frags + g.bfrag_off[layer];
+            const int KBo = rows_out / 16;
+            const int MBi = rows_in / 16;
+            float4_t dz[4][4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) {
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb) {
+                    float4_t c = {0.f, 0.f, 0.f, 0.f};
+                    if (mb < MBi) {
+                        for (int kb = 0; kb < KBo; ++kb) {
+                            half4_t Bv;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) Bv[e] = cur[(16 * kb + 4 * g4 + e) * 64 + 16 * cb + col];
+                            c = __builtin_amdgcn_mfma_f32_16x16x16f16(Bw[(mb * KBo + kb) * 64 + lane], Bv, c, 0, 0, 0);
+                        }
+                        if (layer > 0) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (!((float)act[(16 * mb + 4 * g4 + e) * 64 + 16 * cb + col] > 0.f)) c[e] = 0.f;
+                        }
+                    }
+                    dz[cb][mb] = c;
+                }
+            }
+            if (layer > 0) {
+                float m2 = 0.f;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) m2 = fmaxf(m2, fabsf(dz[cb][mb][e]));
+                const float s2 = pow2_scale(wave_max(m2));
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb)
+                        if (mb < MBi) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                nxt[(16 * mb + 4 * g4 + e) * 64 + 16 * cb + col] = (_Float16)(dz[cb][mb][e] * s2);
+                        }
+                Sc *= s2;
+                __syncthreads();
+                _Float16* t = cur; cur = nxt; nxt = t;
+            } else {
+                // grid scatter: this lane owns levels 8 mb + 2 g4 + {0,1} of walk 16 cb + col
+                const float inv = 1.f / Sc;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const int w = 16 * cb + col;
+                    float xw[D], xh[D];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) xw[d] = __shfl(x[d], w);
+                    normalise_input<D>(g, xw, xh);
+                    const bool wvalid = __shfl((int)valid, w) != 0;
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb) {
+                        if (mb >= kb0) break;
+#pragma unroll
+                        for (int lv = 0; lv < 2; ++lv) {
+                            const int l = 8 * mb + 2 * g4 + lv;
+                            const float gf0 = dz[cb][mb][2 * lv] * inv, gf1 = dz[cb][mb][2 * lv + 1] * inv;
+                            if (!wvalid || (gf0 == 0.f && gf1 == 0.f)) continue;
+                            const int N = g.res[l];
+                            int cc[D];
+                            float fr[D];
+#pragma unroll
+                            for (int d = 0; d < D; ++d) {
+                                const float pos = xh[d] * (float)N;
+                                int ci = (int)floorf(pos);
+                                ci = min(max(ci, 0), N - 1);
+                                cc[d] = ci;
+                                fr[d] = pos - (float)ci;
+                            }
+                            float* gl = a.grad + (int64_t)l * T * 2;
+#pragma unroll
+                            for (int corner = 0; corner < (1 << D); ++corner) {
+                                float wt = 1.f;
+                                uint32_t idx = 0;
+                                if (g.dense[l]) {
+                                    uint32_t stride = 1;
+#pragma unroll
+                                    for (int d = 0; d < D; ++d) {
+                                        const int b = (corner >> d) & 1;
+                                        wt *= b ? fr[d] : 1.f - fr[d];
+                                        idx += (uint32_t)(cc[d] + b) * stride;
+                                        stride *= (uint32_t)(N + 1);
+                                    }
+                                } else {
+                                    const uint32_t primes[3] = {1u, 2654435761u, 805459861u};
+#pragma unroll
+                                    for (int d = 0; d < D; ++d) {
+                                        const int b = (corner >> d) & 1;
+                                        wt *= b ? fr[d] : 1.f - fr[d];
+                                        idx ^= (uint32_t)(cc[d] + b) * primes[d];
+                                    }
+                                    idx &= (uint32_t)(T - 1);
+                                }
+                                atomicAdd(gl + 2 * (int64_t)idx, wt * gf0);
+                                atomicAdd(gl + 2 * (int64_t)idx + 1, wt * gf1);
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (a.loss_sum) {
+        const float s = wave_sum(loss_acc);
+        if (lane == 0) atomicAdd(a.loss_sum, s * a.loss_scale);
+    }
+    if (a.backward) {
+        __syncthreads();
+        float* dst = a.partials + (int64_t)blockIdx.x * a.p_mlp;
+        for (int j = lane; j < a.p_mlp; j += 64) dst[j] = s_dw[j];
+    }
+}
+
+// grad[mlp] += sum over workgroup partials, fixed order (deterministic)
+__global__ void reduce_partials(const float* partials, int nblk, int p_mlp, float* grad_mlp)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= p_mlp) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += partials[(int64_t)b * p_mlp + j];
+    grad_mlp[j] += s;
+}
+
+__global__ void adam_kernel(float* p, float* m, float* v, float* gr, int64_t n, float lr_t, float b1, float b2,
+                            float eps_t)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = gr[i];
+    const float mi = fmaf(b1, m[i], (1.f - b1) * g);
+    const float vi = fmaf(b2, v[i], (1.f - b2) * g * g);
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr_t * mi / (sqrtf(vi) + eps_t);
+    gr[i] = 0.f;
+}
+
+__global__ void zero_f32_t(float* p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+// training target of every record: |V_{k+1}| = |U - prefix_k| / T_{k+1}
+__global__ void tail_pass_kernel(float* rec, int64_t cap, const unsigned long long* count, int dim,
+                                 const float* walk_value, int64_t n_slots)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)min((unsigned long long)cap, *count);
+    if (i >= n) return;
+    const uint32_t slot = __float_as_uint(rec[(int64_t)(3 * dim + 3) * cap + i]);
+    const float pre = rec[(int64_t)(3 * dim + 1) * cap + i];
+    const float tn = rec[(int64_t)(3 * dim + 2) * cap + i];
+    float pt = 0.f;
+    if ((int64_t)slot < n_slots && tn > 0.f) pt = fabsf(walk_value[slot] - pre) / tn;
+    if (!(pt < INFINITY)) pt = 0.f;
+    rec[(int64_t)(3 * dim + 4) * cap + i] = pt;
+}
+
+static int g_train_cu = 0;
+
+static int train_grid_cap()
+{
+    if (g_train_cu == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            g_train_cu = v;
+        else
+            g_train_cu = 256;
+    }
+    return 2 * g_train_cu;
+}
+
+static size_t train_lds_bytes(const wost_guide* gd, bool backward)
+{
+    const GuideDev& g = gd->dev;
+    const int rows_act = 16 * g.kb[0] + 64 * (g.n_layers - 1);
+    const int rmax = g.out_pad > 64 ? g.out_pad : 64;
+    const int64_t p_mlp = gd->n_params - gd->n_grid;
+    size_t b = sizeof(float) * 64 * (g.out_pad + 1) + 2 * (size_t)rows_act * 64 + 2 * 2 * (size_t)rmax * 64;
+    if (backward) b += sizeof(float) * p_mlp;
+    return b;
+}
+
+static int launch_train(const wost_guide* gd, const wost_records* rec, int64_t begin, int64_t count, float e_mis,
+                        float scale, const float* dloss, float* loss_out, float* loss_sum, float loss_scale,
+                        float* grad, void* workspace, int64_t ws_bytes, bool backward, hipStream_t s)
+{
+    GuideDev g;
+    int rc = guide_prepare(gd, gd->cfg.dim, g);
+    if (rc != WOST_OK) return rc;
+    if (!rec || !rec->data || begin < 0 || count < 0 || begin + count > rec->capacity) {
+        set_error("guide training: record range out of bounds");
+        return WOST_EINVAL;
+    }
+    if (count == 0) return WOST_OK;
+    TrainArgs a;
+    memset(&a, 0, sizeof(a));
+    a.rec = rec->data;
+    a.cap = rec->capacity;
+    a.begin = begin;
+    a.count = count;
+    a.e_mis = e_mis;
+    a.scale = scale;
+    a.dloss = dloss;
+    a.loss_out = loss_out;
+    a.loss_sum = loss_sum;
+    a.loss_scale = loss_scale;
+    a.grad = grad;
+    a.backward = backward ? 1 : 0;
+    a.p_mlp = (int32_t)(gd->n_params - gd->n_grid);
+    for (int l = 0; l < g.n_layers; ++l) {
+        a.off[l] = (int32_t)(gd->layer_off[l] - gd->n_grid);
+        a.in[l] = gd->layer_in[l];
+        a.out[l] = gd->layer_out[l];
+    }
+    const int64_t n_tiles = (count + 63) / 64;
+    const int grid = (int)std::min<int64_t>(n_tiles, train_grid_cap());
+    if (backward) {
+        if (!grad) { set_error("guide training: no gradient buffer bound"); return WOST_ESTATE; }
+        const int64_t need = (int64_t)grid * a.p_mlp * 4;
+        if (!workspace || ws_bytes < need) { set_error("guide training: workspace %lld < %lld", (long long)ws_bytes, (long long)need); return WOST_ESIZE; }
+        a.partials = (float*)workspace;
+    }
+    const size_t lds = train_lds_bytes(gd, backward);
+    if (lds > 160 * 1024) { set_error("guide training: configuration needs %zu bytes of LDS", lds); return WOST_EUNSUPPORTED; }
+    if (g.dim == 2) hipLaunchKernelGGL(train_kernel<2>, dim3(grid), dim3(64), lds, s, g, a);
+    else hipLaunchKernelGGL(train_kernel<3>, dim3(grid), dim3(64), lds, s, g, a);
+    if (backward)
+        hipLaunchKernelGGL(reduce_partials, dim3((a.p_mlp + 255) / 256), dim3(256), 0, s, (const float*)a.partials, grid,
+                           a.p_mlp, grad + gd->n_grid);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error("guide training: launch failed: %s", hipGetErrorString(e)); return WOST_EHIP; }
+    return WOST_OK;
+}
+
+}  // namespace wost
+
+using namespace wost;
+
+extern "C" int64_t wost_guide_train_workspace_bytes(const wost_guide* g, int64_t count)
+{
+    if (!g || count < 0) return -1;
+    const int64_t n_tiles = (count + 63) / 64;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_tiles, train_grid_cap()));
+    return grid * (g->n_params - g->n_grid) * 4 + 256;
+}
+
+extern "C" int wost_tail_pass(int32_t dim, const wost_records* rec, const float* walk_value, int64_t n_slots,
+                              void* stream)
+{
+    if ((dim != 2 && dim != 3) || !rec || !rec->data || !rec->count || !walk_value) {
+        set_error("wost_tail_pass: bad arguments");
+        return WOST_EINVAL;
+    }
+    if (rec->capacity == 0) return WOST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(tail_pass_kernel, dim3((unsigned)((rec->capacity + 255) / 256)), dim3(256), 0, s, rec->data,
+                       rec->capacity, (const unsigned long long*)rec->count, dim, walk_value, n_slots);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error("wost_tail_pass: %s", hipGetErrorString(e)); return WOST_EHIP; }
+    return WOST_OK;
+}
+
+extern "C" int wost_guide_loss_fwd(const wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
+                                   float e_mis, float* loss_out, void* stream)
+{
+    if (!g || !loss_out) { set_error("wost_guide_loss_fwd: NULL argument"); return WOST_EINVAL; }
+    return launch_train(g, rec, begin, count, e_mis, 1.f, nullptr, loss_out, nullptr, 0.f, nullptr, nullptr, 0, false,
+                        (hipStream_t)stream);
+}
+
+extern "C" int wost_guide_loss_bwd(const wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
+                                   float e_mis, float scale, const float* dloss, float* grad, void* workspace,
+                                   int64_t ws_bytes, void* stream)
+{
+    if (!g) { set_error("wost_guide_loss_bwd: NULL guide"); return WOST_EINVAL; }
+    float* gr = grad ? grad : g->grad;
+    return launch_train(g, rec, begin, count, e_mis, scale, dloss, nullptr, nullptr, 0.f, gr, workspace, ws_bytes, true,
+                        (hipStream_t)stream);
+}
+
+extern "C" int wost_guide_adam_step(wost_guide* g, const wost_adam* opt, void* stream)
+{
+    if (!g || !opt) { set_error("wost_guide_adam_step: NULL argument"); return WOST_EINVAL; }
+    if (!g->master || !g->adam_m || !g->adam_v || !g->grad) { set_error("wost_guide_adam_step: Adam state not bound"); return WOST_ESTATE; }
+    g->adam_step += 1;
+    const double t = (double)g->adam_step;
+    const double b1 = opt->beta1, b2 = opt->beta2;
+    const double c1 = 1.0 - std::pow(b1, t), c2 = 1.0 - std::pow(b2, t);
+    const float lr_t = (float)(opt->lr * std::sqrt(c2) / c1);
+    const float eps_t = (float)(opt->eps * std::sqrt(c2));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = g->n_params;
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g->master, g->adam_m,
+                       g->adam_v, g->grad, n, lr_t, opt->beta1, opt->beta2, eps_t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error("wost_guide_adam_step: %s", hipGetErrorString(e)); return WOST_EHIP; }
+    return wost_guide_sync_shadow(g, stream);
+}
+
+extern "C" int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
+                                     const wost_adam* opt, float* loss_out, void* workspace, int64_t ws_bytes,
+                                     void* stream)
+{
+    if (!g || !opt) { set_error("wost_guide_train_step: NULL argument"); return WOST_EINVAL; }
+    if (!g->grad || !g->adam_m || !g->adam_v) { set_error("wost_guide_train_step: training state not bound"); return WOST_ESTATE; }
+    if (count <= 0) return WOST_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (loss_out) hipLaunchKernelGGL(zero_f32_t, dim3(1), dim3(64), 0, s, loss_out, (int64_t)1);
+    int rc = launch_train(g, rec, begin, count, opt->e_mis, 1.f / (float)count, nullptr, nullptr, loss_out,
+                          1.f / (float)count, g->grad, workspace, ws_bytes, true, s);
+    if (rc != WOST_OK) return rc;
+    return wost_guide_adam_step(g, opt, stream);
+}
