@@ -1,0 +1,218 @@
+"""Benchmark: guided vs uniform walk on stars on one MI355X.
+
+Workload (default): the 2D mixed problem -- a seeded star-shaped 4096-segment
+outer polygon with Neumann data of u = Re z^3, four circular Dirichlet holes,
+the 256x256 lattice restricted to the domain (43,347 query points), 256 walks
+per point.  One timed step is one guided solve of that workload with a fresh
+guide trained online (batches of walks with the frozen guide and training
+records, tail pass, Adam steps on the hash grid + MLP, repeated), i.e. every
+stage of the hot path.  ``value`` is its end-to-end walk steps per second.
+
+Also reported on the same line: the uniform-sampling solve of the same
+workload, relMSE / MSE of both against the closed form, MSE x time of both,
+the walk kernel's roofline position (algorithmic bytes from instrumented
+traversal counts), and the FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NODE_BYTES = {2: 80, 3: 96}
+PRIM_BYTES = {2: {"dir": 16, "sil": 32, "neu": 32}, 3: {"dir": 48, "sil": 64, "neu": 64}}
+
+
+def rel_mse(est, exact, delta=1e-2):
+    return float(np.mean((est - exact) ** 2 / (exact ** 2 + delta)))
+
+
+def bytes_per_step(cost, dim):
+    """Algorithmic bytes per walk step: hierarchy nodes fetched and primitive
+    records tested by the six queries of a step (counted by the instrumented
+    kernel)."""
+    nb = NODE_BYTES[dim]
+    pb = PRIM_BYTES[dim]
+    kinds = {"closest_dirichlet": pb["dir"], "silhouette": pb["sil"], "neumann_sample": pb["neu"],
+             "neumann_visibility": pb["neu"], "source_visibility": pb["neu"], "first_hit": pb["neu"]}
+    return sum(c["nodes_per_step"] * nb + c["prims_per_step"] * kinds[q] for q, c in cost.items())
+
+
+def cpu_baseline(scene, max_seconds=20.0):
+    import oracle
+    oracle.build(force=False)
+    o = oracle.OracleScene(scene)
+    idx = np.arange(0, scene.n_points, 32)
+    pts = scene.points[idx]
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # calibrate on a small slice, then size the sample to about max_seconds
+    t0 = time.perf_counter()
+    r = o.solve(points=pts[:64], wpp=8, nthreads=cores)
+    dt = time.perf_counter() - t0
+    rate = r["steps"].sum() / max(dt, 1e-6)
+    wpp = int(np.clip(max_seconds * rate / (len(pts) * 14.0), 4, 256))
+    t0 = time.perf_counter()
+    r = o.solve(points=pts, wpp=wpp, nthreads=cores)
+    dt = time.perf_counter() - t0
+    steps = int(r["steps"].sum())
+    return {"value": steps / dt, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
+            "sample": "%d query points (every 32nd lattice point) x %d walks = %d steps, FP64 brute-force, %.1f s"
+                      % (len(pts), wpp, steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--wpp", type=int, default=256)
+    ap.add_argument("--batch-wpp", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the walk-on-stars hot path here runs on a single MI355X "
+              "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2410_18944_amd as W
+    from paper_2410_18944_amd import api
+    from paper_2410_18944_amd.driver import OnlineSchedule, online_solve
+    import scenes
+
+    torch.cuda.set_device(0)
+    s = scenes.scene_c2(wpp=args.wpp)
+    pts = torch.as_tensor(s.points, dtype=torch.float32, device="cuda")
+    u = s.points[:, 0] ** 3 - 3 * s.points[:, 0] * s.points[:, 1] ** 2
+    geom = W.Geometry.from_scene(s)
+    pb_u = W.Problem.from_scene(s)
+    pb_g = W.Problem.from_scene(s, sampling="mis_learned")
+    gcfg = W.GuideConfig.for_scene(s)
+    sched = OnlineSchedule(batch_wpp=args.batch_wpp, train_until_wpp=args.wpp)
+
+    def guided_step(seed):
+        g = W.Guide(gcfg, seed=seed)
+        acc, info = online_solve(geom, pb_g, pts, args.wpp, g, sched, seed=18944 + seed)
+        return acc, info, g
+
+    def uniform_step(seed):
+        acc = W.solve(geom, pb_u, pts, args.wpp, seed=18944 + seed)
+        return acc
+
+    for w in range(args.warmup):
+        guided_step(100 + w)
+        uniform_step(100 + w)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K guided solves
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    total_steps = 0
+    walk_s = train_s = tail_s = 0.0
+    last = None
+    for k in range(args.steps):
+        acc, info, g = guided_step(k + 1)
+        st = acc.stats()
+        total_steps += st["steps"]
+        walk_s += info["phase_s"]["walk"]
+        train_s += info["phase_s"]["train"]
+        tail_s += info["phase_s"]["tail"]
+        last = (acc, info, g)
+    e1.record()
+    torch.cuda.synchronize()
+    elapsed = e0.elapsed_time(e1) * 1e-3
+    wall = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    value = total_steps / elapsed
+
+    acc_g, info_g, g_last = last
+    m_g = acc_g.estimates()[0].cpu().numpy()
+    st_g = acc_g.stats()
+    # ---- uniform solve of the same workload (not part of `value`)
+    u_e0 = torch.cuda.Event(enable_timing=True)
+    u_e1 = torch.cuda.Event(enable_timing=True)
+    u_e0.record()
+    acc_u = uniform_step(1)
+    u_e1.record()
+    torch.cuda.synchronize()
+    t_u = u_e0.elapsed_time(u_e1) * 1e-3
+    m_u = acc_u.estimates()[0].cpu().numpy()
+    st_u = acc_u.stats()
+    t_g = elapsed / args.steps
+    mse_g = float(np.mean((m_g - u) ** 2))
+    mse_u = float(np.mean((m_u - u) ** 2))
+
+    # ---- roofline of the walk kernel: algorithmic bytes per step from an
+    # instrumented pass over a sample of the same workload
+    cost = torch.zeros(12, dtype=torch.int64, device="cuda")
+    api.set_cost_counters(cost)
+    sample = pts[:: max(1, s.n_points // 8192)]
+    a_u = W.solve(geom, pb_u, sample, 16, seed=5)
+    torch.cuda.synchronize()
+    bps_u = bytes_per_step(api.cost_report(cost, a_u.stats()["steps"]), 2)
+    cost.zero_()
+    a_g = W.solve(geom, pb_g, sample, 16, seed=5, guide=g_last)
+    torch.cuda.synchronize()
+    api.set_cost_counters(None)
+    cost_g = api.cost_report(cost, a_g.stats()["steps"])
+    bps_g = bytes_per_step(cost_g, 2)
+    # dominant kernel: the guided walk kernel; time = walk phase of the timed solves
+    achieved = total_steps * bps_g / max(walk_s, 1e-9) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "walk_kernel<2,guided>",
+                "bytes_per_step": round(bps_g, 1), "uniform_bytes_per_step": round(bps_u, 1),
+                "walk_s": round(walk_s, 4), "steps": total_steps}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(s)
+
+    out = {
+        "metric": "walk steps/s (guided WoSt, online training, end-to-end) + MSE x time guided vs uniform",
+        "value": round(value, 1),
+        "unit": "walk steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D mixed Laplace: 4096-segment star polygon (Neumann, Re z^3), 4 Dirichlet holes, "
+                               "256x256 lattice (%d points), %d walks/point, guided (hash grid 8x2x2^16 + MLP 2x64, "
+                               "K=8 vMF, learned MIS, reflection), online training in %d-wpp batches"
+                               % (s.n_points, args.wpp, args.batch_wpp),
+                   "points": s.n_points, "wpp": args.wpp, "seed": 2410},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "guided": {"steps_per_s_end_to_end": round(value, 1), "walk_phase_s": round(walk_s / args.steps, 4),
+                   "train_phase_s": round(train_s / args.steps, 4), "tail_phase_s": round(tail_s / args.steps, 4),
+                   "time_s": round(t_g, 4), "rel_mse": rel_mse(m_g, u), "mse": mse_g, "mse_x_time": mse_g * t_g,
+                   "adam_steps": info_g["adam_steps"], "records": info_g["records"],
+                   "steps_per_walk": st_g["steps"] / max(st_g["walks"], 1)},
+        "uniform": {"steps_per_s": round(st_u["steps"] / t_u, 1), "time_s": round(t_u, 4),
+                    "rel_mse": rel_mse(m_u, u), "mse": mse_u, "mse_x_time": mse_u * t_u,
+                    "steps_per_walk": st_u["steps"] / max(st_u["walks"], 1)},
+        "mse_x_time_speedup_guided_over_uniform": (mse_u * t_u) / max(mse_g * t_g, 1e-300),
+        "wall_s": round(wall, 3),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
