@@ -62,7 +62,7 @@ def _load():
     lib.or_scene_n_silhouette_candidates.restype = C.c_int64
     lib.or_scene_n_silhouette_candidates.argtypes = [P]
     lib.or_solve.restype = C.c_int
-    lib.or_solve.argtypes = [P, C.POINTER(_Problem), dp, C.c_int64, C.c_int32, C.c_uint64, C.c_uint64,
+    lib.or_solve.argtypes = [P, C.POINTER(_Problem), dp, C.c_int64, C.POINTER(C.c_int64), C.c_int32, C.c_uint64, C.c_uint64,
                              dp, dp, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                              dp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int]
     lib.or_walk_trace.restype = C.c_int32
@@ -165,7 +165,7 @@ class OracleScene:
         return pb
 
     def solve(self, points=None, wpp=None, seed=18944, walk_offset=0, per_walk=False,
-              nthreads=0, **problem_kw):
+              nthreads=0, point_ids=None, **problem_kw):
         lib = _load()
         pts = np.ascontiguousarray(self.scene.points if points is None else points, np.float64)
         n = pts.shape[0]
@@ -180,7 +180,11 @@ class OracleScene:
             wv = np.zeros(n * wpp)
             ws = np.zeros(n * wpp, np.int32)
             wst = np.zeros(n * wpp, np.int32)
-        rc = lib.or_solve(self.h, C.byref(pb), _ptr(pts, C.c_double), n, wpp, seed, walk_offset,
+        ids = None if point_ids is None else np.ascontiguousarray(point_ids, np.int64)
+        if ids is not None and ids.shape != (n,):
+            raise ValueError("point_ids must hold one id per point")
+        rc = lib.or_solve(self.h, C.byref(pb), _ptr(pts, C.c_double), n,
+                          _ptr(ids, C.c_int64) if ids is not None else None, wpp, seed, walk_offset,
                           _ptr(su, C.c_double), _ptr(sq, C.c_double), _ptr(cnt, C.c_int64),
                           _ptr(st, C.c_int64),
                           _ptr(wv, C.c_double) if per_walk else None,

@@ -587,10 +587,12 @@ static or_walk_result walk_one(const or_scene* s, const or_problem* pb, const do
  * Walk (p, j) uses the Philox stream keyed by `seed` with counter
  * (p, walk_offset + j, step, block).  Outputs are accumulated (+=) per point:
  * sum, sum of squares, count and total steps.  Optional per-walk arrays are
- * indexed p * wpp + j.  Returns 0 on success.
+ * indexed p * wpp + j.  `point_ids` (optional) replaces p in the counter by
+ * point_ids[p], so a sample of a larger point set reproduces that set's walks.
+ * Returns 0 on success.
  */
 int or_solve(const or_scene* s, const or_problem* pb, const double* pts, int64_t n_points,
-             int32_t wpp, uint64_t seed, uint64_t walk_offset,
+             const int64_t* point_ids, int32_t wpp, uint64_t seed, uint64_t walk_offset,
              double* sum, double* sumsq, int64_t* count, int64_t* steps,
              double* walk_value, int32_t* walk_steps, int32_t* walk_status, int nthreads)
 {
@@ -605,7 +607,8 @@ int or_solve(const or_scene* s, const or_problem* pb, const double* pts, int64_t
         for (int32_t j = 0; j < wpp; ++j) {
             or_rng g;
             g.key[0] = (uint32_t)seed; g.key[1] = (uint32_t)(seed >> 32);
-            g.p = (uint32_t)p; g.j = (uint32_t)(walk_offset + (uint64_t)j);
+            g.p = (uint32_t)(point_ids ? point_ids[p] : p);
+            g.j = (uint32_t)(walk_offset + (uint64_t)j);
             or_walk_result r = walk_one(s, pb, pts + p * s->dim, &g, NULL);
             su += r.value; sq += r.value * r.value; st += r.steps;
             if (walk_value) walk_value[p * wpp + j] = r.value;

@@ -336,8 +336,13 @@ def test_loss_and_backward_match_fp64_reference(W, dim):
 
 
 def test_train_step_fits_known_target(W):
-    """Records with nu uniform and p_t a fixed peaked vMF: Adam on the guide
-    must drive the loss down and the selection probability c up."""
+    """Records with nu uniform and p_t a fixed vMF (kappa = 20) at 16 fixed
+    positions, 4096 records each: Adam on the guide must drive the loss down to
+    near its floor, raise the selection probability c, and put the mixture's
+    mass on the target direction.  The floor is (1 + e) times the target's
+    entropy, since the expected loss is a cross-entropy against a normalised
+    guide; a loss well below it would mean an unnormalised pdf (or records
+    memorised per position, which 4096 records per position rule out)."""
     from oracle import guide_ref as G
     s = _scene_2d()
     cfg = W.GuideConfig.for_scene(s)
@@ -345,12 +350,15 @@ def test_train_step_fits_known_target(W):
     rcfg = _ref_cfg(cfg)
     rng = np.random.default_rng(82)
     n = 1 << 16
+    n_pos = 16
     rec = W.Records(2, capacity=n)
-    x = rng.uniform(rcfg.lo, rcfg.hi, (n, 2))
+    pos = rng.uniform(rcfg.lo + 0.1, rcfg.hi - 0.1, (n_pos, 2))
+    x = np.repeat(pos, n // n_pos, axis=0)
     th = rng.uniform(0, 2 * np.pi, n)
     nu = np.stack([np.cos(th), np.sin(th)], 1)
+    kt = 20.0
     mu_t = np.array([math.cos(0.7), math.sin(0.7)])
-    pt = np.exp(G.vmf_logpdf(nu, mu_t, 20.0))
+    pt = np.exp(G.vmf_logpdf(nu, mu_t, kt))
     D = np.zeros((11, n), np.float32)
     D[0:2] = x.T
     D[2:4] = nu.T
@@ -360,15 +368,22 @@ def test_train_step_fits_known_target(W):
     rec.count.fill_(n)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     losses = []
-    for it in range(300):
+    for it in range(400):
         g.train_step(rec, 0, n, lr=1e-2, loss_out=loss)
-        if it % 50 == 0 or it == 299:
+        if it % 50 == 0 or it == 399:
             losses.append(float(loss.item()))
-    say("known-target losses", losses)
+    # entropy of the 2D vMF: log(2 pi I0e(k)) + k (1 - I1/I0)
+    from scipy.special import i0e, i1e
+    H = math.log(2 * math.pi * i0e(kt)) + kt * (1.0 - i1e(kt) / i0e(kt))
+    floor = 1.2 * H
+    say("known-target losses", losses, "floor %.4f" % floor)
     assert losses[-1] < losses[0] - 0.5
-    y = g.infer(_t(x[:512])).double().cpu().numpy()
+    assert floor - 0.05 < losses[-1] < floor + 0.15, (losses[-1], floor)
+    y = g.infer(_t(pos)).double().cpu().numpy()
     mu, kappa, lam, c = G.map_outputs(y, 2, cfg.K)
-    assert np.median(c) > 0.7
-    # the fitted mixture puts most of its mass near the target mean
-    dens = G.mixture_pdf(mu_t[None], mu[0], kappa[0], lam[0])
-    assert dens > 1.0
+    assert np.median(c) > 0.7, c
+    # the fitted mixture puts its mass near the target mean at every position
+    peak = math.exp(G.vmf_logpdf(mu_t[None], mu_t, kt)[0])
+    dens = np.array([G.mixture_pdf(mu_t[None], mu[i], kappa[i], lam[i])[0] for i in range(n_pos)])
+    say("density at target mean / target peak", np.round(dens / peak, 3))
+    assert np.all(dens > 0.5 * peak), dens / peak

@@ -273,6 +273,12 @@ def test_walk_streams_are_reproducible_and_batch_invariant(oracle_lib):
     wa = a["walk_value"].reshape(16, 16)
     wb = np.concatenate([b1["walk_value"].reshape(16, 8), b2["walk_value"].reshape(16, 8)], 1)
     np.testing.assert_array_equal(wa, wb)
+    # a subset with its original point ids reproduces those rows
+    ids = np.array([3, 11, 14])
+    c = o.solve(points=pts[ids], wpp=16, per_walk=True, point_ids=ids)
+    np.testing.assert_array_equal(c["walk_value"].reshape(3, 16), wa[ids])
+    d = o.solve(points=pts[ids], wpp=16, per_walk=True)
+    assert not np.array_equal(d["walk_value"].reshape(3, 16), wa[ids])
 
 
 def test_tail_recursion_reproduces_forward_sum(oracle_lib):
