@@ -172,7 +172,7 @@ def main():
     achieved = total_steps * bps_g / max(walk_s, 1e-9) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "walk_kernel<2,guided>",
+                "kernel": "wost::walk_kernel2<true, false> (guided 2D walk)",
                 "bytes_per_step": round(bps_g, 1), "uniform_bytes_per_step": round(bps_u, 1),
                 "walk_s": round(walk_s, 4), "steps": total_steps}
 

@@ -296,8 +296,10 @@ int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin,
                           void* stream);
 
 /* ------------------------------------------------------------ launch tuning
- * Persistent walk workgroups per compute unit (default 16; 1..64).  Process
- * wide; affects throughput only, never results. */
+ * Persistent walk workgroups (one wave each) per compute unit, 1..64, or 0
+ * (the default) for as many as the launched kernel variant can keep resident
+ * given its registers and LDS.  Process wide; affects throughput only, never
+ * results. */
 int wost_set_launch(int32_t waves_per_cu);
 /* Traversal-cost instrumentation (process wide).  With a non-NULL device
  * uint64 [12] array, subsequent wost_solve calls run an instrumented kernel

@@ -21,7 +21,7 @@ Contents
   "one_sample_sp"), expressed as a surrogate loss whose autograd gradient equals
   those two estimators.
 
-Readings where the paper is silent (listed in the design doc): kappa' is clamped to
+Readings where the paper is silent: kappa' is clamped to
 [KAPPA_LOG_MIN, KAPPA_LOG_MAX]; mixture output layout per lobe is
 (mu'_1..mu'_d, kappa', lambda') followed by c'; the network is bias-free.
 """
@@ -246,8 +246,9 @@ def grid_corners(cfg: GuideConfig, x):
 
     The cell index is an integer decided by floating point, so the normalised
     position, cell and fractional offsets are computed in float32 with the
-    same operation order as a float32 implementation would (reading listed
-    in the design doc); the weights are then used in float64."""
+    same operation order as a float32 implementation would (both sides take
+    that integer decision in the same precision); the weights are then used
+    in float64."""
     f = np.float32
     x = np.asarray(x, float).astype(f)
     d = cfg.dim

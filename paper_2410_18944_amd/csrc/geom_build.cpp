@@ -423,7 +423,11 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
             }
         }
         // ---- serialise
-        auto fbox = [](const Box& b, int i, bool hi) { return (float)(hi ? b.hi[i] : b.lo[i]); };
+        // boxes round outward by one float step: every primitive stays inside
+        // its float box whatever the rounding of its own vertices
+        auto fbox = [](const Box& b, int i, bool hi) {
+            return hi ? std::nextafter((float)b.hi[i], INFINITY) : std::nextafter((float)b.lo[i], -INFINITY);
+        };
         auto aux = [&](int ni, int ch) {
             if (which == 1) return make_float4((float)sub_meas[ni * 2 + ch], 0.f, 0.f, 0.f);
             if (which == 2) {
@@ -470,11 +474,11 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
                 if (d == 2) {
                     pr.push_back(make_float4((float)a[0], (float)a[1], (float)a[2], (float)a[3]));
                 } else {
-                    double e1[3], e2[3];
-                    for (int i = 0; i < 3; ++i) { e1[i] = a[3 + i] - a[i]; e2[i] = a[6 + i] - a[i]; }
-                    pr.push_back(make_float4((float)a[0], (float)a[1], (float)a[2], (float)e1[0]));
-                    pr.push_back(make_float4((float)e1[1], (float)e1[2], (float)e2[0], (float)e2[1]));
-                    pr.push_back(make_float4((float)e2[2], 0.f, 0.f, 0.f));
+                    // the three vertices as given (rounded once to float), so
+                    // triangles sharing an edge hold bit-identical endpoints
+                    pr.push_back(make_float4((float)a[0], (float)a[1], (float)a[2], (float)a[3]));
+                    pr.push_back(make_float4((float)a[4], (float)a[5], (float)a[6], (float)a[7]));
+                    pr.push_back(make_float4((float)a[8], 0.f, 0.f, 0.f));
                 }
                 if (which == 1)
                     px.push_back(make_float4((float)nout[id][0], (float)nout[id][1], (float)nout[id][2], (float)meas[id]));

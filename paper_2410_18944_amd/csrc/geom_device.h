@@ -152,24 +152,85 @@ __device__ __forceinline__ float closest_tri(const float* x, const float* a, con
     return d2s;
 }
 
+// Per-ray constants of the primitive hit tests.  Both tests are watertight:
+// a ray crossing the boundary where primitives meet (a shared vertex in 2D, a
+// shared edge in 3D) hits at least one of them, so a walker can never slip
+// out of the domain between two primitives.
+template <int D> struct RaySetup;
+template <> struct RaySetup<2> {
+    float x[2], nu[2];
+    __device__ __forceinline__ RaySetup(const float* o, const float* d)
+    {
+        x[0] = o[0]; x[1] = o[1]; nu[0] = d[0]; nu[1] = d[1];
+    }
+    // side of vertex v relative to the ray's line: nu x (v - x).  A function of
+    // (x, nu, v) alone, evaluated without contraction, so both segments that
+    // share v see the same value there.
+    __device__ __forceinline__ float side(float vx, float vy) const
+    {
+#pragma clang fp contract(off)
+        return nu[0] * (vy - x[1]) - nu[1] * (vx - x[0]);
+    }
+};
+// 3D: shear the ray onto +z (Woop, Benthin and Wald, "Watertight Ray/Triangle
+// Intersection", JCGT 2013).  The shear is kept as three row vectors so a
+// vertex maps to (px.v, py.v, pz.v) with no component permutation at run time;
+// the products with 0 and 1 in those rows are exact, so each sheared coordinate
+// is the same single rounding the permuted formulation would give.  These
+// regions switch floating-point contraction off: a fused multiply-add would
+// round the two products of an edge function differently in the two
+// triangles that share the edge.
+template <> struct RaySetup<3> {
+    float x[3], px[3], py[3], pz[3];
+    __device__ __forceinline__ RaySetup(const float* o, const float* d)
+    {
+        const float ax = fabsf(d[0]), ay = fabsf(d[1]), az = fabsf(d[2]);
+        const int kz = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+        int kx = kz == 2 ? 0 : kz + 1, ky = kx == 2 ? 0 : kx + 1;
+        const float dz = kz == 0 ? d[0] : (kz == 1 ? d[1] : d[2]);
+        if (dz < 0.f) { const int t = kx; kx = ky; ky = t; }
+        const float dx = kx == 0 ? d[0] : (kx == 1 ? d[1] : d[2]);
+        const float dy = ky == 0 ? d[0] : (ky == 1 ? d[1] : d[2]);
+        const float sx = dx / dz, sy = dy / dz, sz = 1.f / dz;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            x[i] = o[i];
+            px[i] = (i == kx ? 1.f : 0.f) - (i == kz ? sx : 0.f);
+            py[i] = (i == ky ? 1.f : 0.f) - (i == kz ? sy : 0.f);
+            pz[i] = i == kz ? sz : 0.f;
+        }
+    }
+    __device__ __forceinline__ void shear(const float* v, float& X, float& Y, float& Z) const
+    {
+#pragma clang fp contract(off)
+        const float a0 = v[0] - x[0], a1 = v[1] - x[1], a2 = v[2] - x[2];
+        X = (px[0] * a0 + px[1] * a1) + px[2] * a2;
+        Y = (py[0] * a0 + py[1] * a1) + py[2] * a2;
+        Z = (pz[0] * a0 + pz[1] * a1) + pz[2] * a2;
+    }
+};
+
 template <int D> struct Prim;
-// 2D segment from one float4
+// 2D segment from one float4 (a, b)
 template <> struct Prim<2> {
-    float a[2], e[2];
+    float a[2], b[2], e[2];
     __device__ __forceinline__ void load(const float4* p, int i)
     {
         const float4 s = p[i];
-        a[0] = s.x; a[1] = s.y; e[0] = s.z - s.x; e[1] = s.w - s.y;
+        a[0] = s.x; a[1] = s.y; b[0] = s.z; b[1] = s.w;
+        e[0] = s.z - s.x; e[1] = s.w - s.y;
     }
     __device__ __forceinline__ float closest(const float* x, float* out) const { return closest_seg<2>(x, a, e, out); }
-    // ray x + t nu; returns t or +inf
-    __device__ __forceinline__ float ray(const float* x, const float* nu) const
+    // ray x + t nu against the closed segment; returns t or +inf.  The line
+    // meets the segment iff its endpoints are not strictly on one side (a
+    // segment lying on the line counts as missed).
+    __device__ __forceinline__ float ray(const RaySetup<2>& r) const
     {
-        const float den = nu[0] * e[1] - nu[1] * e[0];
-        const float wx = a[0] - x[0], wy = a[1] - x[1];
-        const float t = (wx * e[1] - wy * e[0]) / den;
-        const float u = (wx * nu[1] - wy * nu[0]) / den;
-        return (den != 0.f && u >= 0.f && u <= 1.f) ? t : INFINITY;
+        const float oa = r.side(a[0], a[1]), ob = r.side(b[0], b[1]);
+        if ((oa > 0.f && ob > 0.f) || (oa < 0.f && ob < 0.f) || (oa == 0.f && ob == 0.f)) return INFINITY;
+        const float s = oa / (oa - ob);   // crossing point a + s e, s in [0, 1]
+        const float cx = fmaf(s, e[0], a[0]) - r.x[0], cy = fmaf(s, e[1], a[1]) - r.x[1];
+        return fmaf(cx, r.nu[0], cy * r.nu[1]);
     }
     __device__ __forceinline__ void point(float s, float, float* z) const
     {
@@ -177,37 +238,45 @@ template <> struct Prim<2> {
         z[1] = fmaf(s, e[1], a[1]);
     }
 };
-// 3D triangle from three float4
+// 3D triangle from three float4 (a, b, c)
 template <> struct Prim<3> {
-    float a[3], e1[3], e2[3];
+    float a[3], b[3], c[3], e1[3], e2[3];
     __device__ __forceinline__ void load(const float4* p, int i)
     {
         const float4 s0 = p[3 * i], s1 = p[3 * i + 1], s2 = p[3 * i + 2];
         a[0] = s0.x; a[1] = s0.y; a[2] = s0.z;
-        e1[0] = s0.w; e1[1] = s1.x; e1[2] = s1.y;
-        e2[0] = s1.z; e2[1] = s1.w; e2[2] = s2.x;
+        b[0] = s0.w; b[1] = s1.x; b[2] = s1.y;
+        c[0] = s1.z; c[1] = s1.w; c[2] = s2.x;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) { e1[k] = b[k] - a[k]; e2[k] = c[k] - a[k]; }
     }
     __device__ __forceinline__ float closest(const float* x, float* out) const { return closest_tri(x, a, e1, e2, out); }
-    // Moller-Trumbore
-    __device__ __forceinline__ float ray(const float* x, const float* nu) const
+    // watertight test in the sheared frame: the edge function of edge (P, Q)
+    // is Q.x P.y - Q.y P.x from uncontracted products, so the two triangles
+    // sharing an edge get exactly opposite values on it
+    __device__ __forceinline__ float ray(const RaySetup<3>& r) const
     {
-        const float p[3] = {nu[1] * e2[2] - nu[2] * e2[1], nu[2] * e2[0] - nu[0] * e2[2], nu[0] * e2[1] - nu[1] * e2[0]};
-        const float det = dot<3>(e1, p);
-        const float inv = 1.f / det;
-        const float tv[3] = {x[0] - a[0], x[1] - a[1], x[2] - a[2]};
-        const float u = dot<3>(tv, p) * inv;
-        const float q[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2], tv[0] * e1[1] - tv[1] * e1[0]};
-        const float v = dot<3>(nu, q) * inv;
-        const float t = dot<3>(e2, q) * inv;
-        return (det != 0.f && u >= 0.f && v >= 0.f && u + v <= 1.f) ? t : INFINITY;
+#pragma clang fp contract(off)
+        float Ax, Ay, Az, Bx, By, Bz, Cx, Cy, Cz;
+        r.shear(a, Ax, Ay, Az);
+        r.shear(b, Bx, By, Bz);
+        r.shear(c, Cx, Cy, Cz);
+        const float U = Cx * By - Cy * Bx;
+        const float V = Ax * Cy - Ay * Cx;
+        const float W = Bx * Ay - By * Ax;
+        if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return INFINITY;
+        const float det = U + V + W;
+        if (det == 0.f) return INFINITY;
+        const float T = fmaf(U, Az, fmaf(V, Bz, W * Cz));
+        return T / det;
     }
     // uniform point on the triangle from two uniforms
     __device__ __forceinline__ void point(float s1, float s2, float* z) const
     {
         const float sq = sqrtf(s1);
-        const float b = sq * (1.f - s2), c = sq * s2;
+        const float u = sq * (1.f - s2), v = sq * s2;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) z[i] = a[i] + b * e1[i] + c * e2[i];
+        for (int i = 0; i < 3; ++i) z[i] = a[i] + u * e1[i] + v * e2[i];
     }
 };
 
@@ -392,7 +461,10 @@ __device__ float closest_silhouette(const DevBvh& b, const float* x, float best2
 
 // ----------------------------------------------------------------- rays
 
-// slab test: entry distance of the ray into the box within [tmin, tmax], or +inf
+// slab test: entry distance of the ray into the box within [tmin, tmax], or
+// +inf.  The exit distance gets a relative slack of 1e-6 (a few roundings of
+// the slab products), so a ray that meets a primitive is never rejected by a
+// flat or grazed box around it.
 template <int D>
 __device__ __forceinline__ float ray_box(const Box<D>& b, const float* x, const float* inv, float tmin, float tmax)
 {
@@ -404,7 +476,7 @@ __device__ __forceinline__ float ray_box(const Box<D>& b, const float* x, const 
         t0 = fmaxf(t0, fminf(a, c));
         t1 = fminf(t1, fmaxf(a, c));
     }
-    return t0 <= t1 ? t0 : INFINITY;
+    return t0 <= t1 * 1.000001f ? t0 : INFINITY;
 }
 
 // first Neumann hit with t in (tau, tmax), skipping internal primitive `skip`;
@@ -422,6 +494,7 @@ __device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, f
     float inv[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) inv[i] = 1.f / nu[i];
+    const RaySetup<D> ry(x, nu);
     float best = tmax;
     int sp = 0, node = 0;
     for (;;) {
@@ -436,7 +509,7 @@ __device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, f
             for (int k = ch.x; k < ch.x + ch.y; ++k) {
                 if (k == skip) continue;
                 Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                const float t = pr.ray(x, nu);
+                const float t = pr.ray(ry);
                 if (t > tau && t < best) { best = t; *hit = k; }
             }
             v0 = false;
@@ -445,7 +518,7 @@ __device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, f
             for (int k = ch.z; k < ch.z + ch.w; ++k) {
                 if (k == skip) continue;
                 Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                const float t = pr.ray(x, nu);
+                const float t = pr.ray(ry);
                 if (t > tau && t < best) { best = t; *hit = k; }
             }
             v1 = false;
@@ -482,6 +555,7 @@ __device__ bool visible_neumann(const DevBvh& b, const float* x, const float* nu
     float inv[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) inv[i] = 1.f / nu[i];
+    const RaySetup<D> ry(x, nu);
     const float tmax = t_hi;
     const float tau = t_lo;
     int sp = 0, node = 0;
@@ -496,7 +570,7 @@ __device__ bool visible_neumann(const DevBvh& b, const float* x, const float* nu
             for (int k = ch.x; k < ch.x + ch.y; ++k) {
                 if (k == skip) continue;
                 Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                const float t = pr.ray(x, nu);
+                const float t = pr.ray(ry);
                 if (t > tau && t < tmax) return false;
             }
             v0 = false;
@@ -505,7 +579,7 @@ __device__ bool visible_neumann(const DevBvh& b, const float* x, const float* nu
             for (int k = ch.z; k < ch.z + ch.w; ++k) {
                 if (k == skip) continue;
                 Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                const float t = pr.ray(x, nu);
+                const float t = pr.ray(ry);
                 if (t > tau && t < tmax) return false;
             }
             v1 = false;

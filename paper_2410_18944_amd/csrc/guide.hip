@@ -37,7 +37,7 @@ __global__ __launch_bounds__(64) void guide_infer_kernel(const GuideDev g, const
 {
     extern __shared__ float s_out[];
     const int lane = threadIdx.x;
-    const int stride = g.out_pad + 1;
+    const int stride = guide_out_stride(g);
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     float x[D];
 #pragma unroll
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(64) void guide_sample_kernel(const GuideDev g, cons
 {
     extern __shared__ float s_out[];
     const int lane = threadIdx.x;
-    const int stride = g.out_pad + 1;
+    const int stride = guide_out_stride(g);
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     float x[D], nin[D];
     bool onN = false;
@@ -283,7 +283,7 @@ extern "C" int wost_guide_infer(const wost_guide* g, const float* pts, int64_t n
     if (n <= 0) return n == 0 ? WOST_OK : WOST_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const unsigned grid = (unsigned)((n + 63) / 64);
-    const size_t lds = sizeof(float) * 64 * (d.out_pad + 1);
+    const size_t lds = sizeof(float) * 64 * guide_out_stride(d);
     if (d.dim == 2) hipLaunchKernelGGL(guide_infer_kernel<2>, dim3(grid), dim3(64), lds, s, d, pts, n, out_raw);
     else hipLaunchKernelGGL(guide_infer_kernel<3>, dim3(grid), dim3(64), lds, s, d, pts, n, out_raw);
     hipError_t e = hipGetLastError();
@@ -308,7 +308,7 @@ extern "C" int wost_guide_sample(const wost_guide* g, int32_t sampling, float c_
     if (n <= 0) return n == 0 ? WOST_OK : WOST_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const unsigned grid = (unsigned)((n + 63) / 64);
-    const size_t lds = sizeof(float) * 64 * (d.out_pad + 1);
+    const size_t lds = sizeof(float) * 64 * guide_out_stride(d);
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     if (d.dim == 2)
         hipLaunchKernelGGL(guide_sample_kernel<2>, dim3(grid), dim3(64), lds, s, d, pts, normals, n, k0, k1, walk_index, out_nu, out_pdf);

@@ -52,6 +52,10 @@ struct GuideDev {
     int32_t reflect;
 };
 
+// row stride (floats) of the per-walk raw outputs in LDS: the outputs
+// themselves, rounded up to an odd count so the 64 rows fall in distinct banks
+__host__ __device__ inline int guide_out_stride(const GuideDev& g) { return g.n_out | 1; }
+
 struct RecDev {
     float* data;
     int64_t capacity;
@@ -143,7 +147,11 @@ __device__ void guide_forward_wave(const GuideDev& g, const float* x, float* lds
         normalise_input<D>(g, xw, xh);
         half4_t act[4];
         const int kb0 = g.kb[0];
-        for (int kb = 0; kb < kb0; ++kb) {
+        // every loop over the four 16-feature blocks is unrolled with a guard,
+        // so the activation fragments stay in registers
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            if (kb >= kb0) break;
             const int l0 = 8 * kb + 2 * g4;
             const float2 f0 = grid_level<D>(g, l0, xh);
             const float2 f1 = grid_level<D>(g, l0 + 1, xh);
@@ -159,8 +167,10 @@ __device__ void guide_forward_wave(const GuideDev& g, const float* x, float* lds
 #pragma unroll
             for (int mb = 0; mb < 4; ++mb) {
                 float4_t c = {0.f, 0.f, 0.f, 0.f};
-                for (int kb = 0; kb < KB; ++kb)
-                    c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
+#pragma unroll
+                for (int kb = 0; kb < 4; ++kb)
+                    if (kb < KB)
+                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
                 half4_t h;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) h[i] = (_Float16)fmaxf(c[i], 0.f);
@@ -176,10 +186,15 @@ __device__ void guide_forward_wave(const GuideDev& g, const float* x, float* lds
             const int KB = g.kb[layer];
             for (int mb = 0; mb < g.mb[layer]; ++mb) {
                 float4_t c = {0.f, 0.f, 0.f, 0.f};
-                for (int kb = 0; kb < KB; ++kb)
-                    c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) lds_out[w * stride + 16 * mb + 4 * g4 + i] = c[i];
+                for (int kb = 0; kb < 4; ++kb)
+                    if (kb < KB)
+                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = 16 * mb + 4 * g4 + i;
+                    if (j < g.n_out) lds_out[w * stride + j] = c[i];
+                }
             }
         }
     }
@@ -222,51 +237,33 @@ __device__ __forceinline__ float vmf_lognorm(float k)
     return logf(k) - logf(2.f * kPi) - logf(-expm1f(-2.f * k));
 }
 
-// mapped lobe parameters read from one lane's raw-output row
+// One lobe of a lane's raw-output row, mapped per Tab. reg_map: unit mean
+// (mu' normalised), concentration exp(kappa') with kappa' clamped.  Lobes are
+// read from the row one at a time, so no per-lane lobe arrays are kept.
 template <int D>
-struct Lobes {
-    static constexpr int MaxK = 16;
-    float mu[MaxK][D];
-    float kappa[MaxK];
-    float lognorm[MaxK];
-    float lam[MaxK];
+struct Lobe {
+    float mu[D];
+    float kappa;
 };
 
 template <int D>
-__device__ __forceinline__ void map_lobes(const float* y, int K, Lobes<D>& L, float* c_raw)
+__device__ __forceinline__ Lobe<D> lobe_at(const float* y, int i)
 {
-    float lmax = -INFINITY;
-    for (int i = 0; i < K; ++i) lmax = fmaxf(lmax, y[i * (D + 2) + D + 1]);
-    float lsum = 0.f;
-    for (int i = 0; i < K; ++i) {
-        const float* r = y + i * (D + 2);
-        float n2 = 0.f;
+    const float* r = y + i * (D + 2);
+    Lobe<D> l;
+    float n2 = 0.f;
 #pragma unroll
-        for (int d = 0; d < D; ++d) n2 = fmaf(r[d], r[d], n2);
-        const float inv = n2 > 0.f ? rsqrtf(n2) : 0.f;
+    for (int d = 0; d < D; ++d) n2 = fmaf(r[d], r[d], n2);
+    const float inv = n2 > 0.f ? rsqrtf(n2) : 0.f;
 #pragma unroll
-        for (int d = 0; d < D; ++d) L.mu[i][d] = n2 > 0.f ? r[d] * inv : (d == 0 ? 1.f : 0.f);
-        const float kp = fminf(fmaxf(r[D], kKappaLogMin), kKappaLogMax);
-        L.kappa[i] = expf(kp);
-        L.lognorm[i] = vmf_lognorm<D>(L.kappa[i]);
-        L.lam[i] = expf(r[D + 1] - lmax);
-        lsum += L.lam[i];
-    }
-    const float il = 1.f / lsum;
-    for (int i = 0; i < K; ++i) L.lam[i] *= il;
-    *c_raw = y[K * (D + 2)];
+    for (int d = 0; d < D; ++d) l.mu[d] = n2 > 0.f ? r[d] * inv : (d == 0 ? 1.f : 0.f);
+    l.kappa = expf(fminf(fmaxf(r[D], kKappaLogMin), kKappaLogMax));
+    return l;
 }
 
+// raw mixture logit of lobe i
 template <int D>
-__device__ __forceinline__ float mixture_pdf(const Lobes<D>& L, int K, const float* nu)
-{
-    float s = 0.f;
-    for (int i = 0; i < K; ++i) {
-        const float c = dot<D>(L.mu[i], nu);
-        s = fmaf(L.lam[i], expf(fmaf(L.kappa[i], c - 1.f, L.lognorm[i])), s);
-    }
-    return s;
-}
+__device__ __forceinline__ float lobe_logit(const float* y, int i) { return y[i * (D + 2) + D + 1]; }
 
 // Best & Fisher (1979) von Mises angle offset; iteration i uses block 4+i.
 __device__ __forceinline__ float von_mises_offset(float k, const Stream& rs, uint32_t step)
@@ -304,13 +301,17 @@ __device__ __forceinline__ void onb(const float* n, float* t1, float* t2)
 // reflected about the tangent plane (Sec. 4.3).  Returns nu and the MIS pdf
 // c p_g(nu) + (1 - c) p_u(nu) of the direction actually used.
 template <int D>
-__device__ void guided_draw(const GuideDev& g, const float* y, const Stream& rs, uint32_t step, const uint4& wd,
-                            bool onN, const float* nin, float* nu, float* pmis)
+__device__ __forceinline__ void guided_draw(const GuideDev& g, const float* y, const Stream& rs, uint32_t step,
+                                            const uint4& wd, bool onN, const float* nin, float* nu, float* pmis)
 {
     const int K = g.K;
-    Lobes<D> L;
-    float craw;
-    map_lobes<D>(y, K, L, &craw);
+    // softmax of the mixture logits: lambda_i = exp(l_i - lmax) / lsum
+    float lmax = -INFINITY;
+    for (int i = 0; i < K; ++i) lmax = fmaxf(lmax, lobe_logit<D>(y, i));
+    float lsum = 0.f;
+    for (int i = 0; i < K; ++i) lsum += expf(lobe_logit<D>(y, i) - lmax);
+    const float il = 1.f / lsum;
+    const float craw = y[K * (D + 2)];
     float c;
     if (g.sampling == WOST_SAMPLING_MIS_LEARNED) c = 1.f / (1.f + expf(-fminf(fmaxf(craw, -kCLogit), kCLogit)));
     else if (g.sampling == WOST_SAMPLING_MIS_FIXED) c = g.c_fixed;
@@ -321,31 +322,35 @@ __device__ void guided_draw(const GuideDev& g, const float* y, const Stream& rs,
         int sel = K - 1;
         float cum = 0.f;
         for (int i = 0; i < K; ++i) {
-            cum += L.lam[i];
+            cum += expf(lobe_logit<D>(y, i) - lmax) * il;
             if (target < cum) { sel = i; break; }
         }
+        const Lobe<D> L = lobe_at<D>(y, sel);
         if (D == 2) {
-            const float psi = von_mises_offset(L.kappa[sel], rs, step);
+            const float psi = von_mises_offset(L.kappa, rs, step);
             float s, co;
             sincosf(psi, &s, &co);
-            nu[0] = co * L.mu[sel][0] - s * L.mu[sel][1];
-            nu[1] = s * L.mu[sel][0] + co * L.mu[sel][1];
+            nu[0] = co * L.mu[0] - s * L.mu[1];
+            nu[1] = s * L.mu[0] + co * L.mu[1];
         } else {
             const uint4 b3 = rs.block(step, kBlkSrc1);
-            const float k = L.kappa[sel];
+            const float k = L.kappa;
             const float sm = -log1pf(u01(b3.y) * expm1f(-2.f * k)) / k;
             const float st = sqrtf(fmaxf(0.f, sm * (2.f - sm)));
             float t1[3], t2[3];
-            onb(L.mu[sel], t1, t2);
+            onb(L.mu, t1, t2);
             float sp, cp;
             sincospif(2.f * u01(b3.z), &sp, &cp);
 #pragma unroll
-            for (int i = 0; i < D; ++i) nu[i] = (1.f - sm) * L.mu[sel][i] + st * (cp * t1[i] + sp * t2[i]);
+            for (int i = 0; i < D; ++i) nu[i] = (1.f - sm) * L.mu[i] + st * (cp * t1[i] + sp * t2[i]);
         }
     } else {
         uniform_dir<D>(u01(wd.x), u01(wd.y), nu);
     }
     const float area = D == 2 ? 2.f * kPi : 4.f * kPi;
+    // reflection into the valid hemisphere on a Neumann boundary; the guided
+    // density of the used direction then sums the lobes at nu and at its mirror
+    float nr[D];
     if (onN) {
         float cn = dot<D>(nu, nin);
         if (cn < 0.f) {
@@ -353,15 +358,19 @@ __device__ void guided_draw(const GuideDev& g, const float* y, const Stream& rs,
             for (int i = 0; i < D; ++i) nu[i] = fmaf(-2.f * cn, nin[i], nu[i]);
             cn = -cn;
         }
-        float nr[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) nr[i] = fmaf(-2.f * cn, nin[i], nu[i]);
-        const float pg = mixture_pdf<D>(L, K, nu) + mixture_pdf<D>(L, K, nr);
-        *pmis = c * pg + (1.f - c) * (2.f / area);
-    } else {
-        const float pg = mixture_pdf<D>(L, K, nu);
-        *pmis = c * pg + (1.f - c) * (1.f / area);
     }
+    float pg = 0.f, pr = 0.f;
+    for (int i = 0; i < K; ++i) {
+        const Lobe<D> L = lobe_at<D>(y, i);
+        const float lam = expf(lobe_logit<D>(y, i) - lmax) * il;
+        const float ln = vmf_lognorm<D>(L.kappa);
+        pg = fmaf(lam, expf(fmaf(L.kappa, dot<D>(L.mu, nu) - 1.f, ln)), pg);
+        if (onN) pr = fmaf(lam, expf(fmaf(L.kappa, dot<D>(L.mu, nr) - 1.f, ln)), pr);
+    }
+    if (onN) *pmis = c * (pg + pr) + (1.f - c) * (2.f / area);
+    else *pmis = c * pg + (1.f - c) * (1.f / area);
 }
 
 }  // namespace wost

@@ -61,16 +61,18 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 }
 
 // LDS bytes of one walk workgroup: the traversal stack and the guide's output
-// transpose are used in different phases of a step and share the space.
-static inline size_t walk_lds_bytes(bool guided, int out_pad)
+// transpose are used in different phases of a step and share the space.  A
+// traversal keeps at most one deferred child per internal level of the path it
+// is on, so the stack needs (deepest hierarchy's depth) entries; one spare.
+static inline size_t walk_lds_bytes(bool guided, int max_depth, int out_stride)
 {
-    const size_t stack = sizeof(uint2) * kMaxStack * kWave;
-    const size_t gout = guided ? sizeof(float) * kWave * (out_pad + 1) : 0;
+    const size_t stack = sizeof(uint2) * (size_t)(max_depth + 1) * kWave;
+    const size_t gout = guided ? sizeof(float) * kWave * (size_t)out_stride : 0;
     return stack > gout ? stack : gout;
 }
 
 template <int D, bool GUIDED, bool STATS>
-__global__ __launch_bounds__(64) void walk_kernel(const WalkParams P)
+__device__ __forceinline__ void walk_body(const WalkParams& P)
 {
     // per-query traversal counters (empty structs unless STATS):
     // 0 closest Dirichlet, 1 silhouette, 2 Neumann sample, 3 Neumann
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(64) void walk_kernel(const WalkParams P)
     const int lane = threadIdx.x;
     const LdsStack st{&s_lds[lane]};
     float* const s_out = (float*)s_lds;
-    const int out_stride = P.guide.out_pad + 1;
+    const int out_stride = guide_out_stride(P.guide);
     const DevGeom& G = P.geom;
 
     bool active = false;
@@ -282,8 +284,11 @@ __global__ __launch_bounds__(64) void walk_kernel(const WalkParams P)
                 for (int i = 0; i < D; ++i) nin[i] = c > 0.f ? -no[i] : no[i];
                 onp = hp;
             } else {
+                // the segment from the ray's origin to this point crosses no
+                // boundary, so the walker stays inside; stepping from x itself
+                // could leave the domain by up to tau along a grazing ray
 #pragma unroll
-                for (int i = 0; i < D; ++i) x[i] = fmaf(r, nu[i], x[i]);
+                for (int i = 0; i < D; ++i) x[i] = fmaf(r, nu[i], xo[i]);
                 onp = -1;
             }
             T *= w;
@@ -357,6 +362,21 @@ __global__ __launch_bounds__(64) void walk_kernel(const WalkParams P)
         const unsigned long long sm = wave_sum_u64(vals[i]);
         if (lane == 0 && sm) atomicAdd(P.counters + i, sm);
     }
+}
+
+// 2D: at least four resident waves per SIMD (<= 128 VGPRs) keeps every
+// variant free of spills.  3D keeps the compiler's choice: its guide encoder
+// (16 levels x 8 corners) would spill under that bound.
+template <bool GUIDED, bool STATS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void walk_kernel2(const WalkParams P)
+{
+    walk_body<2, GUIDED, STATS>(P);
+}
+
+template <bool GUIDED, bool STATS>
+__global__ __launch_bounds__(64) void walk_kernel3(const WalkParams P)
+{
+    walk_body<3, GUIDED, STATS>(P);
 }
 
 __global__ void zero_u64(unsigned long long* p, int n)
@@ -441,7 +461,7 @@ static int num_cu()
     return g_num_cu;
 }
 
-static int g_waves_per_cu = 16;
+static int g_waves_per_cu = 0;   // 0: resident capacity of the launched variant
 static unsigned long long* g_cost = nullptr;
 
 static bool copy_field(const wost_field& in, int dim, FieldDev& out, const char* name)
@@ -488,7 +508,7 @@ extern "C" int wost_set_cost_counters(uint64_t* dev_counters12)
 
 extern "C" int wost_set_launch(int32_t waves_per_cu)
 {
-    if (waves_per_cu < 1 || waves_per_cu > 64) { set_error("wost_set_launch: waves_per_cu in [1, 64]"); return WOST_EINVAL; }
+    if (waves_per_cu < 0 || waves_per_cu > 64) { set_error("wost_set_launch: waves_per_cu in [0, 64]"); return WOST_EINVAL; }
     g_waves_per_cu = waves_per_cu;
     return WOST_OK;
 }
@@ -567,29 +587,28 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     }
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, P.work, 1);
+    using WalkFn = void (*)(const WalkParams);
+    WalkFn fn;
+    if (dim == 2) {
+        if (P.cost) fn = guided ? walk_kernel2<true, true> : walk_kernel2<false, true>;
+        else fn = guided ? walk_kernel2<true, false> : walk_kernel2<false, false>;
+    } else {
+        if (P.cost) fn = guided ? walk_kernel3<true, true> : walk_kernel3<false, true>;
+        else fn = guided ? walk_kernel3<true, false> : walk_kernel3<false, false>;
+    }
+    const size_t lds = walk_lds_bytes(guided, geom->max_depth, guide_out_stride(P.guide));
+    int per_cu = g_waves_per_cu;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64, lds) != hipSuccess || nb < 1) nb = 8;
+        per_cu = nb;
+    }
     const uint64_t waves_needed = (P.n_walks + 63) / 64;
-    const uint64_t cap = (uint64_t)num_cu() * (uint64_t)g_waves_per_cu;
+    const uint64_t cap = (uint64_t)num_cu() * (uint64_t)per_cu;
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(waves_needed, cap));
     // about eight reservations per wave over the whole call, at least one lane's worth each
     P.chunk = std::max<uint64_t>(64, std::min<uint64_t>(4096, P.n_walks / ((uint64_t)grid * 8)));
-    const size_t lds = walk_lds_bytes(guided, P.guide.out_pad);
-    if (dim == 2) {
-        if (P.cost) {
-            if (guided) hipLaunchKernelGGL((walk_kernel<2, true, true>), dim3(grid), dim3(64), lds, s, P);
-            else hipLaunchKernelGGL((walk_kernel<2, false, true>), dim3(grid), dim3(64), lds, s, P);
-        } else {
-            if (guided) hipLaunchKernelGGL((walk_kernel<2, true, false>), dim3(grid), dim3(64), lds, s, P);
-            else hipLaunchKernelGGL((walk_kernel<2, false, false>), dim3(grid), dim3(64), lds, s, P);
-        }
-    } else {
-        if (P.cost) {
-            if (guided) hipLaunchKernelGGL((walk_kernel<3, true, true>), dim3(grid), dim3(64), lds, s, P);
-            else hipLaunchKernelGGL((walk_kernel<3, false, true>), dim3(grid), dim3(64), lds, s, P);
-        } else {
-            if (guided) hipLaunchKernelGGL((walk_kernel<3, true, false>), dim3(grid), dim3(64), lds, s, P);
-            else hipLaunchKernelGGL((walk_kernel<3, false, false>), dim3(grid), dim3(64), lds, s, P);
-        }
-    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(64), lds, s, P);
     const int rgrid = (int)((n_points + 3) / 4);
     hipLaunchKernelGGL(reduce_points, dim3(rgrid), dim3(256), 0, s, P.slot_value, n_points, wpp, sum, sum_sq, count);
     hipError_t e = hipGetLastError();

@@ -39,7 +39,7 @@ template <> struct NodeT<3> { using type = Node3; };
 
 // Primitive records.
 //  2D segment: float4 (a.x, a.y, b.x, b.y)
-//  3D triangle: 3 x float4: (a.xyz, e1.x) (e1.yz, e2.xy) (e2.z, pad...)
+//  3D triangle: 3 x float4: (a.xyz, b.x) (b.yz, c.xy) (c.z, pad...)
 //  Neumann extra per primitive: float4 (n_out.xyz (2D: xy,0), measure)
 //  Silhouette 2D: 2 x float4: (v.xy, n1.xy) (n2.xy, q1, q2)
 //  Silhouette 3D: 4 x float4: (a.xyz, b.x) (b.yz, n1.xy) (n1.z, n2.xyz) (q1, q2, 0, 0)

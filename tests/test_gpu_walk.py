@@ -110,6 +110,100 @@ def test_query_parity_3d_sphere(W, O):
     _query_case(W, O, s, pts, dirs, 3.0)
 
 
+def _closed_neumann_rays(W, s, pts, targets):
+    """Rays from interior points aimed (in float32) exactly at boundary
+    features of a closed, all-Neumann boundary: every one must hit."""
+    pts = np.asarray(pts, np.float32)
+    d = np.asarray(targets, np.float32) - pts
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    geom = W.Geometry.from_scene(s)
+    q = geom.query(_t(pts), ray_dir=_t(d), ray_tmax=10.0)
+    torch.cuda.synchronize()
+    hit = q["ray_prim"].cpu().numpy() >= 0
+    t = q["ray_t"].cpu().numpy()
+    dist = np.linalg.norm(np.asarray(targets, np.float64) - pts, axis=1)
+    return hit, t, dist
+
+
+def test_rays_through_vertices_and_edges_never_escape(W):
+    """Watertight primitive tests: a ray that crosses the boundary exactly
+    where two segments (2D) or two triangles (3D) meet hits at least one of
+    them, so no ray from inside a closed boundary escapes.  (A ray grazing a
+    silhouette vertex may pass it, so only the hit itself is required.)"""
+    rng = np.random.default_rng(31)
+    s = rounded(scenes.scene_c2())
+    s.bc = np.ones_like(s.bc)                   # every primitive Neumann: a closed set of ray targets
+    outer = s.prims[:4096]                      # the outer polygon comes first
+    v = s.verts[outer[:, 0]]
+    n = 1 << 17
+    p = s.points[rng.integers(0, s.n_points, n)]
+    tgt = v[rng.integers(0, len(v), n)]
+    hit, t, _ = _closed_neumann_rays(W, s, p, tgt)
+    say("2D vertex rays: misses %d of %d" % ((~hit).sum(), n))
+    assert hit.all() and np.all((t > 0) & np.isfinite(t))
+    P, T = scenes.geodesic_sphere(24)
+    P = np.asarray(P, np.float32).astype(np.float64)
+    s3 = scenes.Scene("sphere24", 3, P, T, np.ones(len(T), np.uint8), np.zeros((1, 3)), g=(0, np.zeros(0)),
+                      h=(0, np.zeros(0)), f=(0, np.zeros(0)), u_exact=(0, np.zeros(0)))
+    p3 = rng.normal(size=(n, 3))
+    p3 = p3 / np.linalg.norm(p3, axis=1, keepdims=True) * rng.uniform(0, 0.9, (n, 1))
+    tri = T[rng.integers(0, len(T), n)]
+    k = rng.integers(0, 3, n)
+    a, b = P[tri[np.arange(n), k]], P[tri[np.arange(n), (k + 1) % 3]]
+    tgt3 = np.where((rng.random(n) < 0.5)[:, None], a, 0.5 * (a + b))   # vertices and edge midpoints
+    hit3, t3, _ = _closed_neumann_rays(W, s3, p3, tgt3)
+    say("3D vertex/edge rays: misses %d of %d" % ((~hit3).sum(), n))
+    assert hit3.all() and np.all((t3 > 0) & np.isfinite(t3))
+
+
+def test_walkers_stay_inside_the_domain(W, O):
+    """A walker on the Neumann boundary tests its ray from a point tau inside
+    along its normal; on a miss it must also move from that point.  Moving
+    from the boundary point itself along a grazing direction once left the
+    domain (seed 18945, point 42067, walk 99 of the 2D mixed scene: 34 steps
+    in the oracle, 1062 on the GPU while it wandered off to infinity).  Every
+    recorded position of 42k walks (guided sampling with c = 0, which draws
+    the uniform directions) must lie inside the outer polygon or within 1e-5
+    of it, and outside the holes."""
+    from matplotlib.path import Path
+    s = rounded(scenes.scene_c2())
+    p, j, seed = 42067, 99, 18945
+    n = p + 1
+    geom = W.Geometry.from_scene(s)
+    g = W.Guide(W.GuideConfig.for_scene(s), seed=3)
+    pb = W.Problem.from_scene(s, sampling="mis_fixed", c_fixed=0.0)
+    rec = W.Records(2, capacity=n * 48)
+    wv = torch.empty(n, dtype=torch.float32, device="cuda")
+    ws = torch.empty(n, dtype=torch.int32, device="cuda")
+    acc = W.solve(geom, pb, _t(s.points[:n]), 1, seed=seed, walk_offset=j, guide=g, walk_value=wv, walk_steps=ws,
+                  records=rec)
+    torch.cuda.synchronize()
+    st = acc.stats()
+    say("walks", st)
+    steps = ws.cpu().numpy()
+    o = O.OracleScene(s).solve(points=s.points[[p]], wpp=1, seed=seed, walk_offset=j, per_walk=True, point_ids=[p])
+    assert steps[p] == o["walk_steps"][0], (steps[p], o["walk_steps"][0])
+    assert st["records_dropped"] == 0 and np.all(np.isfinite(wv.cpu().numpy()))
+    x = rec.data[0:2, :rec.n()].double().cpu().numpy().T
+    outer = s.verts[s.prims[:4096, 0]]
+    inside = Path(outer).contains_points(x)
+    out = x[~inside]
+    if len(out):
+        a, b = s.verts[s.prims[:4096, 0]], s.verts[s.prims[:4096, 1]]
+        e = b - a
+        ee = (e * e).sum(-1)[None]
+        dmax = 0.0
+        for c in range(0, len(out), 512):
+            w = out[c:c + 512, None, :] - a[None]
+            t = np.clip((w * e[None]).sum(-1) / ee, 0, 1)
+            dmax = max(dmax, float(np.linalg.norm(w - t[..., None] * e[None], axis=-1).min(1).max()))
+        say("positions outside the outer polygon: %d, max distance %.3e" % (len(out), dmax))
+        assert dmax < 1e-5
+    for h in range(4):
+        ring = s.verts[s.prims[4096 + 256 * h: 4096 + 256 * (h + 1), 0]]
+        assert not Path(ring).contains_points(x).any()
+
+
 # ----------------------------------------------------------------------------- walks
 
 def _gpu_solve(W, s, wpp, seed=18944, per_walk=True, points=None, **pkw):
@@ -184,34 +278,51 @@ def test_c2_trajectories_and_estimates_vs_oracle(W, O):
     assert np.mean(np.abs(z) > 3) < 0.02 and abs(z.mean()) < 5 / np.sqrt(len(z)), (z.mean(), np.abs(z).max())
 
 
-def test_c2_full_grid_matches_re_z3(W):
-    s = scenes.scene_c2()
-    say("C2 full grid, 256 wpp", s.n_points)
-    g = _gpu_solve(W, s, 256, per_walk=False)
-    u = exact_solution(s, s.points)
-    # Near the holes ~1% of walks make long excursions that carry most of the
-    # variance; a point whose 256 walks happen to contain none gets both a
-    # shifted mean and a tiny sample SE.  The SE therefore comes from an
-    # independent run (1024 walks, other seed), and deviations up to the
-    # epsilon-shell bias eps |grad u| are allowed.
-    v = _gpu_solve(W, s, 1024, seed=7, per_walk=False)
-    se_ind = v["se"] * np.sqrt(1024.0 / 256.0)
-    P = s.points
-    grad = np.hypot(3 * (P[:, 0] ** 2 - P[:, 1] ** 2), 6 * P[:, 0] * P[:, 1])
-    allow = s.eps * grad
-    z = (g["mean"] - u) / se_ind
-    worst = np.argsort(-np.abs(z))[:12]
-    for i in worst:
-        say("worst z %.2f at point %d %s: mean %.5f exact %.5f se %.5f" % (z[i], i, s.points[i], g["mean"][i], u[i],
-                                                                         g["se"][i]))
-    import os
-    os.makedirs("gpurun_out", exist_ok=True)
-    np.savez("gpurun_out/c2_full_grid.npz", mean=g["mean"], se=g["se"], exact=u, points=s.points)
-    zscore_check(g["mean"], se_ind, u, g["n"], label="C2 gpu", allow=allow, var_band=(0.5, 1.35))
-    # the 1024-walk run against the closed form as well
-    zscore_check(v["mean"], v["se"], u, v["n"], label="C2 gpu 1024", allow=allow, var_band=(0.5, 1.35))
+def test_c2_full_grid_sampled_parity_and_bounds(W, O):
+    """The full 2D workload (43,347 points x 256 walks, default launch shape)
+    checked on a seeded sample of points that the oracle recomputes walk by
+    walk under the same point ids, and on properties that hold at any size:
+    every walk and step is counted, no value is non-finite, and the grid
+    average of (estimate - closed form) stays within the epsilon-shell bias
+    bound eps * sup |grad u| near the Dirichlet boundary plus 5 standard
+    errors.  (Per-point z-scores are not used here: near the holes about 1% of
+    walks make long excursions that carry most of the variance, so a point's
+    sample SE is itself heavy-tailed.)"""
+    s = rounded(scenes.scene_c2())
+    wpp = 256
+    say("C2 full grid", s.n_points, "x", wpp)
+    g = _gpu_solve(W, s, wpp)
     st = g["stats"]
-    assert st["walks"] == s.n_points * 256 and st["nonfinite"] == 0
+    assert st["walks"] == s.n_points * wpp and st["nonfinite"] == 0
+    assert st["steps"] == int(g["walk_steps"].sum())
+    assert np.all(np.isfinite(g["walk_value"]))
+    rng = np.random.default_rng(2411)
+    ids = np.sort(rng.choice(s.n_points, 48, replace=False))
+    o = O.OracleScene(s).solve(points=s.points[ids], wpp=wpp, per_walk=True, point_ids=ids)
+    gv = g["walk_value"].reshape(-1, wpp)[ids]
+    gs = g["walk_steps"].reshape(-1, wpp)[ids].ravel()
+    gv = gv.ravel()
+    same = gs == o["walk_steps"]
+    say("sampled walks with identical step counts: %.4f" % same.mean())
+    assert same.mean() > 0.97, same.mean()
+    # the path of a walk is fixed by its Philox words; its Neumann terms are
+    # drawn by different valid samplers on the two sides (BVH descent here,
+    # area-weighted selection in the oracle), so per-walk values are not
+    # unique and only their per-point means are compared
+    mg = gv.reshape(-1, wpp).mean(1)
+    sg = gv.reshape(-1, wpp).std(1, ddof=1) / np.sqrt(wpp)
+    mo, so, _ = O.estimates(o)
+    z = two_sample_z(mg, sg, mo, so)
+    say("sampled points: two-sample |z| max %.2f, mean z %.3f" % (np.abs(z).max(), z.mean()))
+    assert np.mean(np.abs(z) > 3) < 0.05 and abs(z.mean()) < 5 / np.sqrt(len(z)), z
+    u = exact_solution(s, s.points)
+    dev = g["mean"] - u
+    se_glob = np.sqrt(np.sum(g["se"] ** 2)) / s.n_points
+    dir_verts = np.unique(s.prims[s.bc == 0])          # per-primitive codes: 0 = Dirichlet
+    rmax = np.max(np.linalg.norm(s.verts[dir_verts], axis=1)) + s.eps
+    bound = s.eps * 3.0 * rmax ** 2 + 5.0 * se_glob
+    say("grid mean deviation %.3e (SE %.3e, bound %.3e)" % (dev.mean(), se_glob, bound))
+    assert abs(dev.mean()) <= bound
 
 
 def test_cube_3d_on_gpu(W, O):
