@@ -5,8 +5,9 @@ outer polygon with Neumann data of u = Re z^3, four circular Dirichlet holes,
 the 256x256 lattice restricted to the domain (43,347 query points), 256 walks
 per point.  One timed step is one guided solve of that workload with a fresh
 guide trained online (batches of walks with the frozen guide and training
-records, tail pass, Adam steps on the hash grid + MLP, repeated), i.e. every
-stage of the hot path.  ``value`` is its end-to-end walk steps per second.
+records, tail pass, Adam steps on the hash grid + MLP, repeated for the first
+quarter of the walks, then inference-only walks), i.e. every stage of the hot
+path.  ``value`` is its end-to-end walk steps per second.
 
 Also reported on the same line: the uniform-sampling solve of the same
 workload, relMSE / MSE of both against the closed form, MSE x time of both,
@@ -75,9 +76,23 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--wpp", type=int, default=256)
-    ap.add_argument("--batch-wpp", type=int, default=4)
+    ap.add_argument("--batch-wpp", type=int, default=16)
+    ap.add_argument("--train-until", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_probe_mib > 0:
+        import torch
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_mib": args.copy_probe_mib, "bytes_read_per_copy": 4 * n,
+                          "bytes_written_per_copy": 4 * n, "copies": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the walk-on-stars hot path here runs on a single MI355X "
               "(--gpus %d is not supported)" % args.gpus, file=sys.stderr)
@@ -98,7 +113,7 @@ def main():
     pb_u = W.Problem.from_scene(s)
     pb_g = W.Problem.from_scene(s, sampling="mis_learned")
     gcfg = W.GuideConfig.for_scene(s)
-    sched = OnlineSchedule(batch_wpp=args.batch_wpp, train_until_wpp=args.wpp)
+    sched = OnlineSchedule(batch_wpp=args.batch_wpp, train_until_wpp=args.train_until)
 
     def guided_step(seed):
         g = W.Guide(gcfg, seed=seed)
@@ -121,12 +136,14 @@ def main():
     e0.record()
     total_steps = 0
     walk_s = train_s = tail_s = 0.0
+    n_launch = 0
     last = None
     for k in range(args.steps):
         acc, info, g = guided_step(k + 1)
         st = acc.stats()
         total_steps += st["steps"]
         walk_s += info["phase_s"]["walk"]
+        n_launch += info["walk_launches"]
         train_s += info["phase_s"]["train"]
         tail_s += info["phase_s"]["tail"]
         last = (acc, info, g)
@@ -174,7 +191,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "wost::walk_kernel2<true, false> (guided 2D walk)",
                 "bytes_per_step": round(bps_g, 1), "uniform_bytes_per_step": round(bps_u, 1),
-                "walk_s": round(walk_s, 4), "steps": total_steps}
+                "walk_s": round(walk_s, 4), "steps": total_steps,
+                "launches": n_launch, "avg_launch_ms": round(walk_s / max(n_launch, 1) * 1e3, 3)}
 
     cpu = None
     if not args.no_cpu:
@@ -195,8 +213,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "2D mixed Laplace: 4096-segment star polygon (Neumann, Re z^3), 4 Dirichlet holes, "
                                "256x256 lattice (%d points), %d walks/point, guided (hash grid 8x2x2^16 + MLP 2x64, "
-                               "K=8 vMF, learned MIS, reflection), online training in %d-wpp batches"
-                               % (s.n_points, args.wpp, args.batch_wpp),
+                               "K=8 vMF, learned MIS, reflection), online training in %d-wpp batches for the first %d wpp"
+                               % (s.n_points, args.wpp, args.batch_wpp, args.train_until),
                    "points": s.n_points, "wpp": args.wpp, "seed": 2410},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -78,8 +78,10 @@ class Geometry:
         return cls(scene.dim, scene.verts, scene.prims, scene.bc, **kw)
 
     def __del__(self):
-        if getattr(self, "h", None) is not None and L._lib is not None:
-            L._lib.wost_geom_free(self.h)
+        # at interpreter shutdown the binding module may already be torn down
+        lib = getattr(L, "_lib", None) if L is not None else None
+        if getattr(self, "h", None) is not None and lib is not None:
+            lib.wost_geom_free(self.h)
             self.h = None
 
     def query(self, pts, dirichlet=True, silhouette=True, ray_dir=None, ray_tmax=None):

@@ -431,8 +431,14 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
         auto aux = [&](int ni, int ch) {
             if (which == 1) return make_float4((float)sub_meas[ni * 2 + ch], 0.f, 0.f, 0.f);
             if (which == 2) {
+                // normal cone as (axis, cos of the half-angle); cos <= 0 marks
+                // a cone that never culls (half-angle >= pi/2, or a subtree
+                // holding a boundary feature).  The cosine is rounded down so
+                // the stored cone contains the exact one.
                 auto& c = sub_cone[ni * 2 + ch];
-                return make_float4((float)c[0], (float)c[1], (float)c[2], (float)c[3]);
+                const double ch_ = std::cos(c[3]);
+                const float cw = c[3] >= 0.5 * M_PI ? -1.f : std::nextafter((float)ch_, -INFINITY);
+                return make_float4((float)c[0], (float)c[1], (float)c[2], cw);
             }
             return make_float4(0.f, 0.f, 0.f, 0.f);
         };

@@ -101,7 +101,10 @@ __device__ __forceinline__ float closest_seg(const float* x, const float* a, con
 #pragma unroll
     for (int i = 0; i < D; ++i) w[i] = x[i] - a[i];
     const float ee = dot<D>(e, e);
-    float t = ee > 0.f ? dot<D>(w, e) / ee : 0.f;
+    // parameter of the projection, clamped to the segment; the hardware
+    // reciprocal (1 ulp) is enough for a value that is clamped and only
+    // places the closest point
+    float t = ee > 0.f ? dot<D>(w, e) * __builtin_amdgcn_rcpf(ee) : 0.f;
     t = fminf(fmaxf(t, 0.f), 1.f);
     float d2 = 0.f;
 #pragma unroll
@@ -228,7 +231,9 @@ template <> struct Prim<2> {
     {
         const float oa = r.side(a[0], a[1]), ob = r.side(b[0], b[1]);
         if ((oa > 0.f && ob > 0.f) || (oa < 0.f && ob < 0.f) || (oa == 0.f && ob == 0.f)) return INFINITY;
-        const float s = oa / (oa - ob);   // crossing point a + s e, s in [0, 1]
+        // crossing point a + s e; the hit decision above is exact, the
+        // parameter only places the point (hardware reciprocal, clamped)
+        const float s = fminf(fmaxf(oa * __builtin_amdgcn_rcpf(oa - ob), 0.f), 1.f);
         const float cx = fmaf(s, e[0], a[0]) - r.x[0], cy = fmaf(s, e[1], a[1]) - r.x[1];
         return fmaf(cx, r.nu[0], cy * r.nu[1]);
     }
@@ -356,25 +361,29 @@ __device__ float closest_dirichlet(const DevBvh& b, const float* x, float best2,
 template <int D>
 __device__ __forceinline__ bool cone_culls(const Box<D>& b, const float4& cone, const float* x)
 {
-    if (cone.w >= 1.5707963f) return false;
-    float c[D], v[D], R2 = 0.f, dist2 = 0.f;
+    // cone = (axis, cos theta).  With v = x - c for the box's bounding sphere
+    // (centre c, radius R), every point p of the sphere and every normal n of
+    // the cone keep (x - p).n of one sign iff the angle beta between v and the
+    // axis stays more than theta + phi away from pi/2, phi = asin(R / |v|).
+    // Without trigonometry: require theta + phi < pi/2 (R < |v| cos theta) and
+    //   |v.axis| > |v| sin(theta + phi) = sin(theta) sqrt(|v|^2 - R^2) + cos(theta) R,
+    // plus a margin of 1e-3 |v| (about 1e-3 rad of beta) for rounding.
+    const float ct = cone.w;
+    if (!(ct > 0.f)) return false;
+    float v[D], R2 = 0.f, dist2 = 0.f, va = 0.f;
+    const float ax[3] = {cone.x, cone.y, cone.z};
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-        c[i] = 0.5f * (b.lo[i] + b.hi[i]);
         const float h = 0.5f * (b.hi[i] - b.lo[i]);
         R2 = fmaf(h, h, R2);
-        v[i] = x[i] - c[i];
+        v[i] = x[i] - 0.5f * (b.lo[i] + b.hi[i]);
         dist2 = fmaf(v[i], v[i], dist2);
+        va = fmaf(v[i], ax[i], va);
     }
-    if (dist2 <= R2 * 1.0001f + 1e-30f) return false;
-    const float dist = sqrtf(dist2);
-    const float phi = asinf(fminf(sqrtf(R2) / dist, 1.f));
-    const float ax[3] = {cone.x, cone.y, cone.z};
-    const float cb = fminf(fmaxf(dot<D>(v, ax) / dist, -1.f), 1.f);
-    const float beta = acosf(cb);
-    const float margin = 1e-3f;
-    const float spread = cone.w + phi + margin;
-    return (beta + spread < 1.5707963f) || (beta - spread > 1.5707963f);
+    if (!(R2 < dist2 * ct * ct)) return false;
+    const float st = sqrtf(fmaxf(1.f - ct * ct, 0.f));
+    const float bound = fmaf(st, sqrtf(dist2 - R2), ct * sqrtf(R2)) + 1e-3f * sqrtf(dist2);
+    return fabsf(va) > bound;
 }
 
 // Silhouette candidate k seen from x.  A Neumann primitive faces x from the

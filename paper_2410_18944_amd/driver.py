@@ -23,16 +23,23 @@ from .guide import Guide, tail_pass
 
 @dataclasses.dataclass
 class OnlineSchedule:
-    batch_wpp: int = 4               # walks per point per training batch
-    train_until_wpp: int = 256       # stop training after this many walks per point
+    """Training schedule.  The paper trains on the first 256 of 1024 walks per
+    point in batches of one walk per point over a 1024^2 grid (Sec. 5.2,
+    Sec. 6.1); here the default trains on the first quarter of the walks
+    (``train_fraction``) in batches of 16 walks per point, so that a batch
+    over tens of thousands of points still fills the GPU and its longest walk
+    does not leave most lanes idle."""
+    batch_wpp: int = 16              # walks per point per training batch
+    train_until_wpp: int = 0         # stop training after this many walks per point (0: use train_fraction)
+    train_fraction: float = 0.25     # share of the walks that train the guide when train_until_wpp is 0
     minibatch: int = 1 << 18         # records per Adam step
-    max_steps_per_batch: int = 8     # Adam steps per batch (records are subsampled beyond)
+    max_steps_per_batch: int = 16    # Adam steps per batch (records are subsampled beyond)
     lr: float = 1e-2
     beta1: float = 0.9
     beta2: float = 0.999
     adam_eps: float = 1e-8
     e_mis: float = 0.2
-    records_per_walk: float = 24.0   # record capacity per walk (overflow is dropped and counted)
+    records_per_walk: float = 64.0   # record capacity per walk (overflow is dropped and counted)
 
 
 class Timer:
@@ -64,7 +71,8 @@ def online_solve(geom, problem, pts, wpp_total, guide: Guide, schedule: OnlineSc
     dim = pts.shape[1]
     acc = acc if acc is not None else api.Accumulator(n, pts.device)
     timer = timer or Timer()
-    train_wpp = min(sch.train_until_wpp, wpp_total)
+    until = sch.train_until_wpp if sch.train_until_wpp > 0 else int(round(sch.train_fraction * wpp_total))
+    train_wpp = min(until, wpp_total)
     b = max(1, min(sch.batch_wpp, train_wpp)) if train_wpp > 0 else 0
     cap = int(n * b * sch.records_per_walk) if b else 0
     rec = api.Records(dim, cap, pts.device) if b else None
@@ -109,5 +117,6 @@ def online_solve(geom, problem, pts, wpp_total, guide: Guide, schedule: OnlineSc
     info["wall_s"] = time.perf_counter() - t0
     info["phase_s"] = timer.totals({"walk": ("walk0", "walk1"), "tail": ("walk1", "tail1"),
                                     "train": ("train0", "train1")})
+    info["walk_launches"] = len(timer.events.get("walk0", []))
     info["losses"] = [float(x.item()) for x in info["losses"]]
     return acc, info
