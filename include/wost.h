@@ -302,13 +302,15 @@ int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin,
  * results. */
 int wost_set_launch(int32_t waves_per_cu);
 /* Traversal-cost instrumentation (process wide).  With a non-NULL device
- * uint64 [12] array, subsequent wost_solve calls run an instrumented kernel
- * variant that accumulates, per query type, hierarchy nodes fetched and
- * primitives tested: [2q] nodes, [2q+1] primitives for q = 0 closest
- * Dirichlet point, 1 closest silhouette, 2 Neumann sample, 3 Neumann
- * visibility, 4 source visibility, 5 first hit.  NULL switches it off.
+ * uint64 [18] array, subsequent wost_solve calls run an instrumented kernel
+ * variant that accumulates, per query type q (0 closest Dirichlet point,
+ * 1 closest silhouette, 2 Neumann sample, 3 Neumann visibility, 4 source
+ * visibility, 5 first hit): [2q] hierarchy nodes fetched and [2q+1]
+ * primitives tested, summed over lanes; [12+q] wave-level loop iterations,
+ * the sum over wave steps of the largest per-lane node count (a wave runs a
+ * traversal for as long as its slowest lane).  NULL switches it off.
  * Results are unchanged; only throughput differs. */
-int wost_set_cost_counters(uint64_t* dev_counters12);
+int wost_set_cost_counters(uint64_t* dev_counters18);
 
 #ifdef __cplusplus
 }

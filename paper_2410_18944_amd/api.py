@@ -216,12 +216,18 @@ COST_QUERIES = ["closest_dirichlet", "silhouette", "neumann_sample", "neumann_vi
 
 
 def set_cost_counters(counters):
-    """Enable (int64 device tensor of 12) or disable (None) traversal-cost counting."""
+    """Enable (int64 device tensor of 18) or disable (None) traversal-cost counting."""
+    if counters is not None and counters.numel() < 18:
+        raise ValueError("cost counters need 18 int64 entries")
     L.check(L.load().wost_set_cost_counters(_ptr(counters) if counters is not None else None),
             "wost_set_cost_counters")
 
 
 def cost_report(counters, steps):
+    """Per query: nodes and primitives per walk step (lane sums), and the
+    wave-level iteration count relative to a perfectly packed wave
+    (64 x wave iterations / lane node visits; 1 means no divergence loss)."""
     c = counters.cpu().numpy().astype(float)
-    return {q: dict(nodes_per_step=c[2 * i] / steps, prims_per_step=c[2 * i + 1] / steps)
+    return {q: dict(nodes_per_step=c[2 * i] / steps, prims_per_step=c[2 * i + 1] / steps,
+                    wave_iters=c[12 + i], divergence=64.0 * c[12 + i] / max(c[2 * i], 1.0))
             for i, q in enumerate(COST_QUERIES)}

@@ -35,6 +35,8 @@ template <int D> struct Box { float lo[D], hi[D]; };
 struct NoStat {};
 struct Stat {
     uint32_t nodes = 0, prims = 0;
+    uint32_t step0 = 0;             // nodes at the start of the current walk step
+    unsigned long long witer = 0;   // wave-level iterations (lane 0 only)
 };
 __device__ __forceinline__ void stat_node(NoStat*) {}
 __device__ __forceinline__ void stat_prim(NoStat*) {}
@@ -473,7 +475,8 @@ __device__ float closest_silhouette(const DevBvh& b, const float* x, float best2
 // slab test: entry distance of the ray into the box within [tmin, tmax], or
 // +inf.  The exit distance gets a relative slack of 1e-6 (a few roundings of
 // the slab products), so a ray that meets a primitive is never rejected by a
-// flat or grazed box around it.
+// flat or grazed box around it.  tmin may be negative (crossings just behind
+// the origin).
 template <int D>
 __device__ __forceinline__ float ray_box(const Box<D>& b, const float* x, const float* inv, float tmin, float tmax)
 {
@@ -485,16 +488,29 @@ __device__ __forceinline__ float ray_box(const Box<D>& b, const float* x, const 
         t0 = fmaxf(t0, fminf(a, c));
         t1 = fminf(t1, fmaxf(a, c));
     }
-    return t0 <= t1 * 1.000001f ? t0 : INFINITY;
+    return t0 <= t1 + 1e-6f * fabsf(t1) ? t0 : INFINITY;
+}
+
+// true if direction nu leaves the domain through Neumann primitive k
+template <int D>
+__device__ __forceinline__ bool exits(const DevBvh& b, int k, const float* nu)
+{
+    const float4 e = b.pextra[k];
+    const float no[3] = {e.x, e.y, e.z};
+    return dot<D>(no, nu) > 0.f;
 }
 
 // first Neumann hit with t in (tau, tmax), skipping internal primitive `skip`;
 // returns t (or +inf) and the hit primitive (or -1).  Walk rays pass tau = 0:
 // a walker standing on the boundary shoots from an origin offset along its
 // normal instead, so no genuine crossing near the origin is ever ignored.
+// With back > 0 a crossing at t in (-back, tau] also counts if the ray leaves
+// the domain through it (nu . n_out > 0): seen from inside, the first crossing
+// is always an exit, so an exit at or just behind the origin means the origin
+// lies on the boundary up to rounding, and the walker is put back onto it.
 template <int D, class S = NoStat>
 __device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, float tmax, float tau, int skip,
-                             int* hit, const LdsStack& st, S* s = nullptr)
+                             int* hit, const LdsStack& st, S* s = nullptr, float back = 0.f)
 {
     using NodeType = typename NodeT<D>::type;
     const NodeType* nodes = (const NodeType*)b.nodes;
@@ -511,15 +527,15 @@ __device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, f
         int4 ch;
         load_node_boxes<D>(nodes, node, b0, b1, ch);
         stat_node(s);
-        const float e0 = ch.x >= 0 ? ray_box<D>(b0, x, inv, 0.f, best) : INFINITY;
-        const float e1 = ch.z >= 0 ? ray_box<D>(b1, x, inv, 0.f, best) : INFINITY;
+        const float e0 = ch.x >= 0 ? ray_box<D>(b0, x, inv, -back, best) : INFINITY;
+        const float e1 = ch.z >= 0 ? ray_box<D>(b1, x, inv, -back, best) : INFINITY;
         bool v0 = e0 < INFINITY, v1 = e1 < INFINITY;
         if (v0 && ch.y > 0) {
             for (int k = ch.x; k < ch.x + ch.y; ++k) {
                 if (k == skip) continue;
                 Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
                 const float t = pr.ray(ry);
-                if (t > tau && t < best) { best = t; *hit = k; }
+                if (t < best && (t > tau || (t > -back && exits<D>(b, k, nu)))) { best = t; *hit = k; }
             }
             v0 = false;
         }
@@ -528,7 +544,7 @@ __device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, f
                 if (k == skip) continue;
                 Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
                 const float t = pr.ray(ry);
-                if (t > tau && t < best) { best = t; *hit = k; }
+                if (t < best && (t > tau || (t > -back && exits<D>(b, k, nu)))) { best = t; *hit = k; }
             }
             v1 = false;
         }

@@ -50,6 +50,16 @@ __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
 #pragma unroll
@@ -141,6 +151,10 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             }
         }
         if (__ballot(active) == 0) break;
+        if constexpr (STATS) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) sq[q].step0 = sq[q].nodes;
+        }
 
         // ---- phase A: closest Dirichlet point, epsilon-shell / step-cap termination
         bool stepping = false, finish = false;
@@ -273,15 +287,20 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             for (int i = 0; i < D; ++i) { rec_x[i] = x[i]; rec_nin[i] = onN ? nin[i] : 0.f; }
             // first hit inside the star
             int hp;
-            const float t = ray_neumann<D>(G.neu, xo, nu, r, 0.f, onp, &hp, st, &sq[5]);
+            // the search runs to r + tau, so a boundary point at distance r
+            // (a silhouette point straight ahead) puts the walker on the
+            // boundary, and exits up to tau behind the origin count (the
+            // origin is then on the boundary up to rounding)
+            const float t = ray_neumann<D>(G.neu, xo, nu, r + G.tau, 0.f, onp, &hp, st, &sq[5], G.tau);
             if (hp >= 0) {
 #pragma unroll
                 for (int i = 0; i < D; ++i) x[i] = fmaf(t, nu[i], xo[i]);
+                // the walk's side of a Neumann primitive is the domain, so its
+                // normal toward the walk is -n_out (a first hit seen from
+                // inside is always an exit, nu . n_out > 0)
                 const float4 ex = G.neu.pextra[hp];
-                const float no[3] = {ex.x, ex.y, ex.z};
-                const float c = dot<D>(no, nu);
 #pragma unroll
-                for (int i = 0; i < D; ++i) nin[i] = c > 0.f ? -no[i] : no[i];
+                for (int i = 0; i < D; ++i) nin[i] = -(i == 0 ? ex.x : (i == 1 ? ex.y : ex.z));
                 onp = hp;
             } else {
                 // the segment from the ray's origin to this point crosses no
@@ -302,6 +321,16 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             rec_prefix = acc;
             rec_tnext = T;
             do_rec = GUIDED && P.rec.data != nullptr;
+        }
+
+        // wave-level iterations of each query this step: the wave runs a
+        // traversal loop for as long as its slowest lane
+        if constexpr (STATS) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                const uint32_t m = wave_max_u32(sq[q].nodes - sq[q].step0);
+                if (lane == 0) sq[q].witer += m;
+            }
         }
 
         // ---- phase E: training record append (one atomic per wave)
@@ -353,6 +382,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             if (lane == 0) {
                 atomicAdd(P.cost + 2 * q, a);
                 atomicAdd(P.cost + 2 * q + 1, b);
+                atomicAdd(P.cost + 12 + q, sq[q].witer);
             }
         }
     }
@@ -500,9 +530,9 @@ extern "C" int64_t wost_solve_workspace_bytes(const wost_geom* geom, int64_t n_p
     return 256 + ((n_points * (int64_t)wpp * 4 + 255) & ~int64_t(255));
 }
 
-extern "C" int wost_set_cost_counters(uint64_t* dev_counters12)
+extern "C" int wost_set_cost_counters(uint64_t* dev_counters18)
 {
-    g_cost = (unsigned long long*)dev_counters12;
+    g_cost = (unsigned long long*)dev_counters18;
     return WOST_OK;
 }
 

@@ -73,8 +73,10 @@ class Guide:
         L.check(lib.wost_guide_init(h, int(seed), _stream()), "wost_guide_init")
 
     def __del__(self):
-        if getattr(self, "h", None) is not None and L._lib is not None:
-            L._lib.wost_guide_free(self.h)
+        # at interpreter shutdown the binding module may already be torn down
+        lib = getattr(L, "_lib", None) if L is not None else None
+        if getattr(self, "h", None) is not None and lib is not None:
+            lib.wost_guide_free(self.h)
             self.h = None
 
     def set_params(self, flat):

@@ -156,18 +156,23 @@ def test_rays_through_vertices_and_edges_never_escape(W):
     assert hit3.all() and np.all((t3 > 0) & np.isfinite(t3))
 
 
-def test_walkers_stay_inside_the_domain(W, O):
-    """A walker on the Neumann boundary tests its ray from a point tau inside
-    along its normal; on a miss it must also move from that point.  Moving
-    from the boundary point itself along a grazing direction once left the
-    domain (seed 18945, point 42067, walk 99 of the 2D mixed scene: 34 steps
-    in the oracle, 1062 on the GPU while it wandered off to infinity).  Every
-    recorded position of 42k walks (guided sampling with c = 0, which draws
-    the uniform directions) must lie inside the outer polygon or within 1e-5
-    of it, and outside the holes."""
+@pytest.mark.parametrize("p,j,seed", [(42067, 99, 18945), (41704, 100, 2)])
+def test_walkers_stay_inside_the_domain(W, O, p, j, seed):
+    """Two walks of the 2D mixed scene that once left the domain on the GPU
+    and then wandered off to infinity (the oracle finishes them in a few
+    dozen steps):
+      - seed 18945, point 42067, walk 99: a walker on the Neumann boundary
+        tests its ray from a point tau inside along its normal but moved from
+        the boundary point itself, and a grazing direction took it outside;
+      - seed 2, point 41704, walk 100: a ray met the boundary at exactly the
+        star radius, so the walker stopped on the boundary without being
+        marked as on it, and its next ray's exit at t ~ 1e-8 rounded to t <= 0.
+    Both must now follow the oracle's walk.  Every recorded position of the
+    p + 1 walks of the launch (guided sampling with c = 0, which draws the
+    uniform directions) must lie inside the outer polygon or within 1e-5 of
+    it, and outside the holes."""
     from matplotlib.path import Path
     s = rounded(scenes.scene_c2())
-    p, j, seed = 42067, 99, 18945
     n = p + 1
     geom = W.Geometry.from_scene(s)
     g = W.Guide(W.GuideConfig.for_scene(s), seed=3)
