@@ -168,7 +168,11 @@ typedef struct {
     int64_t* count;         /* device */
 } wost_records;
 
-/* Workspace bytes needed by wost_solve for n_points x wpp walks. */
+/* Workspace bytes needed by wost_solve for n_points x wpp walks: a walk
+ * counter, one float per walk, and the walk pools of the persistent kernel
+ * (per wave, a structure of arrays of up to `slots_per_wave` walks plus its
+ * work lists; see wost_set_walk_pool).  The figure depends on the device's
+ * compute-unit count and the pool setting at the time of the call. */
 int64_t wost_solve_workspace_bytes(const wost_geom* geom, int64_t n_points, int32_t wpp);
 
 /* Walk-on-stars solve (Sec. 3.2 estimator; Sec. 4 guided directions).
@@ -301,6 +305,15 @@ int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin,
  * given its registers and LDS.  Process wide; affects throughput only, never
  * results. */
 int wost_set_launch(int32_t waves_per_cu);
+/* Walk pool of the persistent kernel.  Each wave keeps `slots_per_wave`
+ * walks in flight (a multiple of 64 in [64, 8192]; 0 = default 512) and
+ * advances all of them one star per round, query by query; a lane whose
+ * query has finished takes the next walk of that query's list, once at least
+ * `refill_batch` lanes (1..64; 0 = default 16) are waiting or no lane is
+ * still traversing.  Larger pools keep more lanes busy at the cost of
+ * workspace.  Process wide; affects throughput and workspace size only,
+ * never results.  Call wost_solve_workspace_bytes after changing it. */
+int wost_set_walk_pool(int32_t slots_per_wave, int32_t refill_batch);
 /* Traversal-cost instrumentation (process wide).  With a non-NULL device
  * uint64 [18] array, subsequent wost_solve calls run an instrumented kernel
  * variant that accumulates, per query type q (0 closest Dirichlet point,

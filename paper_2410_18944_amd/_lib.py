@@ -70,6 +70,7 @@ SIGNATURES = {
     "wost_solve": (_I, [_P, C.POINTER(wost_problem), _P, _I64, _I32, _U64, _U64, _P, _P, _P, _P, _P, _P,
                         C.POINTER(wost_records), _P, _I64, _P, _P]),
     "wost_set_launch": (_I, [_I32]),
+    "wost_set_walk_pool": (_I, [_I32, _I32]),
     "wost_set_cost_counters": (_I, [_P]),
     "wost_guide_create": (_I, [C.POINTER(wost_guide_config), C.POINTER(_P)]),
     "wost_guide_param_count": (_I64, [_P]),

@@ -207,6 +207,12 @@ def solve(geom, problem, pts, wpp, seed=18944, walk_offset=0, guide=None, acc=No
     return acc
 
 
+def set_walk_pool(slots_per_wave=0, refill_batch=0):
+    """Walk slots per persistent wave (multiple of 64; 0 = default 512) and
+    the number of finished lanes that refill together (0 = default 16)."""
+    L.check(L.load().wost_set_walk_pool(int(slots_per_wave), int(refill_batch)), "wost_set_walk_pool")
+
+
 def set_launch(waves_per_cu):
     L.check(L.load().wost_set_launch(int(waves_per_cu)), "wost_set_launch")
 

@@ -287,71 +287,86 @@ template <> struct Prim<3> {
     }
 };
 
-// ----------------------------------------------------------------- closest point
+// ----------------------------------------------------------------- traversals
+//
+// Every query is resumable: its state is a small struct, begin() sets it up
+// and step() visits one node (testing the primitives of leaf children
+// inline), returning true once the query has finished.  A lane can therefore
+// interleave queries of different walks; the run-to-completion functions
+// further down loop over step(), so every caller runs the same code.
 
-// Returns the squared distance (< best2 on entry to count as found) and the
-// closest point; prim_out = internal primitive id or -1.
-template <int D, class S = NoStat>
-__device__ float closest_dirichlet(const DevBvh& b, const float* x, float best2, float* xbar, int* prim_out,
-                                   const LdsStack& st, S* s = nullptr)
+// Binary-tree traversal state: current node (-1 when finished), stack depth,
+// best key so far and the primitive that attained it.
+struct Trav {
+    int node, sp;
+    float best;
+    int prim;
+};
+
+// After the children of a node were tested: descend into the nearer live
+// child and defer the other, or resume from the deepest deferred entry whose
+// key is still below `best`.  Returns false when nothing is left.
+__device__ __forceinline__ bool trav_next(bool v0, bool v1, float k0, float k1, const int4& ch, float best,
+                                          Trav& q, const LdsStack& st)
 {
-    using NodeType = typename NodeT<D>::type;
-    const NodeType* nodes = (const NodeType*)b.nodes;
-    int bp = -1;
-    if (b.n_nodes == 0) { *prim_out = -1; return best2; }
-    int sp = 0, node = 0;
-    for (;;) {
-        Box<D> b0, b1;
-        int4 ch;
-        load_node_boxes<D>(nodes, node, b0, b1, ch);
-        stat_node(s);
-        float d0 = box_dist2<D>(b0, x), d1 = box_dist2<D>(b1, x);
-        bool v0 = d0 < best2, v1 = d1 < best2;
-        if (v0 && ch.y > 0) {
-            for (int k = ch.x; k < ch.x + ch.y; ++k) {
-                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                float c[D];
-                const float dd = pr.closest(x, c);
-                if (dd < best2) {
-                    best2 = dd; bp = k;
-#pragma unroll
-                    for (int i = 0; i < D; ++i) xbar[i] = c[i];
-                }
-            }
-            v0 = false;
-        }
-        if (v1 && ch.w > 0) {
-            for (int k = ch.z; k < ch.z + ch.w; ++k) {
-                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                float c[D];
-                const float dd = pr.closest(x, c);
-                if (dd < best2) {
-                    best2 = dd; bp = k;
-#pragma unroll
-                    for (int i = 0; i < D; ++i) xbar[i] = c[i];
-                }
-            }
-            v1 = false;
-        }
-        v0 = v0 && d0 < best2;
-        v1 = v1 && d1 < best2;
-        if (v0 && v1) {
-            const bool first0 = d0 <= d1;
-            st.put(sp++, first0 ? ch.z : ch.x, first0 ? d1 : d0);
-            node = first0 ? ch.x : ch.z;
-            continue;
-        }
-        if (v0) { node = ch.x; continue; }
-        if (v1) { node = ch.z; continue; }
-        bool found = false;
-        while (sp > 0) {
-            const uint2 e = st.get(--sp);
-            if (__uint_as_float(e.y) < best2) { node = (int)e.x; found = true; break; }
-        }
-        if (!found) break;
+    if (v0 && v1) {
+        const bool first0 = k0 <= k1;
+        st.put(q.sp++, first0 ? ch.z : ch.x, first0 ? k1 : k0);
+        q.node = first0 ? ch.x : ch.z;
+        return true;
     }
-    *prim_out = bp;
-    return best2;
+    if (v0) { q.node = ch.x; return true; }
+    if (v1) { q.node = ch.z; return true; }
+    while (q.sp > 0) {
+        const uint2 e = st.get(--q.sp);
+        if (__uint_as_float(e.y) < best) { q.node = (int)e.x; return true; }
+    }
+    q.node = -1;
+    return false;
+}
+
+__device__ __forceinline__ void trav_begin(const DevBvh& b, float best, Trav& q)
+{
+    q.node = b.n_nodes > 0 ? 0 : -1;
+    q.sp = 0;
+    q.best = best;
+    q.prim = -1;
+}
+
+// ---- closest Dirichlet point: q.best = squared distance, q.prim = primitive
+template <int D, class S>
+__device__ __forceinline__ bool closest_dirichlet_step(const DevBvh& b, const float* x, Trav& q, const LdsStack& st,
+                                                       S* s)
+{
+    if (q.node < 0) return true;
+    using NodeType = typename NodeT<D>::type;
+    Box<D> b0, b1;
+    int4 ch;
+    load_node_boxes<D>((const NodeType*)b.nodes, q.node, b0, b1, ch);
+    stat_node(s);
+    const float d0 = box_dist2<D>(b0, x), d1 = box_dist2<D>(b1, x);
+    bool v0 = d0 < q.best, v1 = d1 < q.best;
+    if (v0 && ch.y > 0) {
+        for (int k = ch.x; k < ch.x + ch.y; ++k) {
+            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+            float c[D];
+            const float dd = pr.closest(x, c);
+            if (dd < q.best) { q.best = dd; q.prim = k; }
+        }
+        v0 = false;
+    }
+    if (v1 && ch.w > 0) {
+        for (int k = ch.z; k < ch.z + ch.w; ++k) {
+            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+            float c[D];
+            const float dd = pr.closest(x, c);
+            if (dd < q.best) { q.best = dd; q.prim = k; }
+        }
+        v1 = false;
+    }
+    v0 = v0 && d0 < q.best;
+    v1 = v1 && d1 < q.best;
+    return !trav_next(v0, v1, d0, d1, ch, q.best, q, st);
 }
 
 // ----------------------------------------------------------------- silhouettes
@@ -425,49 +440,32 @@ __device__ __forceinline__ float sil_prim_dist2(const float4* p, int k, const fl
     return closest_seg<D>(x, a, e, c);
 }
 
-template <int D, class S = NoStat>
-__device__ float closest_silhouette(const DevBvh& b, const float* x, float best2, int onp, const LdsStack& st,
-                                    S* s = nullptr)
+// ---- closest silhouette: q.best = squared distance (starts at the bound)
+template <int D, class S>
+__device__ __forceinline__ bool closest_silhouette_step(const DevBvh& b, const float* x, int onp, Trav& q,
+                                                        const LdsStack& st, S* s)
 {
+    if (q.node < 0) return true;
     using NodeType = typename NodeT<D>::type;
-    const NodeType* nodes = (const NodeType*)b.nodes;
-    if (b.n_nodes == 0) return best2;
-    int sp = 0, node = 0;
-    for (;;) {
-        Box<D> b0, b1;
-        int4 ch;
-        float4 c0, c1;
-        load_node(nodes, node, b0, b1, ch, c0, c1);
-        stat_node(s);
-        float d0 = box_dist2<D>(b0, x), d1 = box_dist2<D>(b1, x);
-        bool v0 = d0 < best2 && !cone_culls<D>(b0, c0, x);
-        bool v1 = d1 < best2 && !cone_culls<D>(b1, c1, x);
-        if (v0 && ch.y > 0) {
-            for (int k = ch.x; k < ch.x + ch.y; ++k) best2 = fminf(best2, sil_prim_dist2<D>(b.prims, k, x, onp)), stat_prim(s);
-            v0 = false;
-        }
-        if (v1 && ch.w > 0) {
-            for (int k = ch.z; k < ch.z + ch.w; ++k) best2 = fminf(best2, sil_prim_dist2<D>(b.prims, k, x, onp)), stat_prim(s);
-            v1 = false;
-        }
-        v0 = v0 && d0 < best2;
-        v1 = v1 && d1 < best2;
-        if (v0 && v1) {
-            const bool first0 = d0 <= d1;
-            st.put(sp++, first0 ? ch.z : ch.x, first0 ? d1 : d0);
-            node = first0 ? ch.x : ch.z;
-            continue;
-        }
-        if (v0) { node = ch.x; continue; }
-        if (v1) { node = ch.z; continue; }
-        bool found = false;
-        while (sp > 0) {
-            const uint2 e = st.get(--sp);
-            if (__uint_as_float(e.y) < best2) { node = (int)e.x; found = true; break; }
-        }
-        if (!found) break;
+    Box<D> b0, b1;
+    int4 ch;
+    float4 c0, c1;
+    load_node((const NodeType*)b.nodes, q.node, b0, b1, ch, c0, c1);
+    stat_node(s);
+    const float d0 = box_dist2<D>(b0, x), d1 = box_dist2<D>(b1, x);
+    bool v0 = d0 < q.best && !cone_culls<D>(b0, c0, x);
+    bool v1 = d1 < q.best && !cone_culls<D>(b1, c1, x);
+    if (v0 && ch.y > 0) {
+        for (int k = ch.x; k < ch.x + ch.y; ++k) q.best = fminf(q.best, sil_prim_dist2<D>(b.prims, k, x, onp)), stat_prim(s);
+        v0 = false;
     }
-    return best2;
+    if (v1 && ch.w > 0) {
+        for (int k = ch.z; k < ch.z + ch.w; ++k) q.best = fminf(q.best, sil_prim_dist2<D>(b.prims, k, x, onp)), stat_prim(s);
+        v1 = false;
+    }
+    v0 = v0 && d0 < q.best;
+    v1 = v1 && d1 < q.best;
+    return !trav_next(v0, v1, d0, d1, ch, q.best, q, st);
 }
 
 // ----------------------------------------------------------------- rays
@@ -500,122 +498,103 @@ __device__ __forceinline__ bool exits(const DevBvh& b, int k, const float* nu)
     return dot<D>(no, nu) > 0.f;
 }
 
-// first Neumann hit with t in (tau, tmax), skipping internal primitive `skip`;
-// returns t (or +inf) and the hit primitive (or -1).  Walk rays pass tau = 0:
-// a walker standing on the boundary shoots from an origin offset along its
-// normal instead, so no genuine crossing near the origin is ever ignored.
-// With back > 0 a crossing at t in (-back, tau] also counts if the ray leaves
-// the domain through it (nu . n_out > 0): seen from inside, the first crossing
-// is always an exit, so an exit at or just behind the origin means the origin
-// lies on the boundary up to rounding, and the walker is put back onto it.
-template <int D, class S = NoStat>
-__device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, float tmax, float tau, int skip,
-                             int* hit, const LdsStack& st, S* s = nullptr, float back = 0.f)
-{
-    using NodeType = typename NodeT<D>::type;
-    const NodeType* nodes = (const NodeType*)b.nodes;
-    *hit = -1;
-    if (b.n_nodes == 0) return INFINITY;
+// Ray state: traversal state plus the reciprocal direction of the slabs.
+// q.best = nearest accepted t, q.prim = hit primitive.
+template <int D>
+struct RayTrav {
+    Trav t;
     float inv[D];
+};
+
+template <int D>
+__device__ __forceinline__ void ray_begin(const DevBvh& b, const float* nu, float tmax, RayTrav<D>& q)
+{
+    trav_begin(b, tmax, q.t);
 #pragma unroll
-    for (int i = 0; i < D; ++i) inv[i] = 1.f / nu[i];
-    const RaySetup<D> ry(x, nu);
-    float best = tmax;
-    int sp = 0, node = 0;
-    for (;;) {
-        Box<D> b0, b1;
-        int4 ch;
-        load_node_boxes<D>(nodes, node, b0, b1, ch);
-        stat_node(s);
-        const float e0 = ch.x >= 0 ? ray_box<D>(b0, x, inv, -back, best) : INFINITY;
-        const float e1 = ch.z >= 0 ? ray_box<D>(b1, x, inv, -back, best) : INFINITY;
-        bool v0 = e0 < INFINITY, v1 = e1 < INFINITY;
-        if (v0 && ch.y > 0) {
-            for (int k = ch.x; k < ch.x + ch.y; ++k) {
-                if (k == skip) continue;
-                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                const float t = pr.ray(ry);
-                if (t < best && (t > tau || (t > -back && exits<D>(b, k, nu)))) { best = t; *hit = k; }
-            }
-            v0 = false;
-        }
-        if (v1 && ch.w > 0) {
-            for (int k = ch.z; k < ch.z + ch.w; ++k) {
-                if (k == skip) continue;
-                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                const float t = pr.ray(ry);
-                if (t < best && (t > tau || (t > -back && exits<D>(b, k, nu)))) { best = t; *hit = k; }
-            }
-            v1 = false;
-        }
-        v0 = v0 && e0 < best;
-        v1 = v1 && e1 < best;
-        if (v0 && v1) {
-            const bool first0 = e0 <= e1;
-            st.put(sp++, first0 ? ch.z : ch.x, first0 ? e1 : e0);
-            node = first0 ? ch.x : ch.z;
-            continue;
-        }
-        if (v0) { node = ch.x; continue; }
-        if (v1) { node = ch.z; continue; }
-        bool found = false;
-        while (sp > 0) {
-            const uint2 e = st.get(--sp);
-            if (__uint_as_float(e.y) < best) { node = (int)e.x; found = true; break; }
-        }
-        if (!found) break;
-    }
-    return *hit >= 0 ? best : INFINITY;
+    for (int i = 0; i < D; ++i) q.inv[i] = 1.f / nu[i];
 }
 
-// no Neumann primitive other than `skip` crosses the ray x + t nu (unit nu)
-// at a parameter t in (t_lo, t_hi)
-template <int D, class S = NoStat>
-__device__ bool visible_neumann(const DevBvh& b, const float* x, const float* nu, float t_lo, float t_hi, int skip,
-                                const LdsStack& st, S* s = nullptr)
+// ---- first Neumann hit with t in (tau, tmax), skipping internal primitive
+// `skip`.  Walk rays pass tau = 0: a walker standing on the boundary shoots
+// from an origin offset along its normal instead, so no genuine crossing near
+// the origin is ever ignored.  With back > 0 a crossing at t in (-back, tau]
+// also counts if the ray leaves the domain through it (nu . n_out > 0): seen
+// from inside, the first crossing is always an exit, so an exit at or just
+// behind the origin means the origin lies on the boundary up to rounding, and
+// the walker is put back onto it.
+template <int D, class S>
+__device__ __forceinline__ bool ray_neumann_step(const DevBvh& b, const float* x, const float* nu, float tau,
+                                                 float back, int skip, RayTrav<D>& q, const LdsStack& st, S* s)
 {
+    if (q.t.node < 0) return true;
     using NodeType = typename NodeT<D>::type;
-    const NodeType* nodes = (const NodeType*)b.nodes;
-    if (b.n_nodes == 0) return true;
-    float inv[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) inv[i] = 1.f / nu[i];
     const RaySetup<D> ry(x, nu);
-    const float tmax = t_hi;
-    const float tau = t_lo;
-    int sp = 0, node = 0;
-    for (;;) {
-        Box<D> b0, b1;
-        int4 ch;
-        load_node_boxes<D>(nodes, node, b0, b1, ch);
-        stat_node(s);
-        bool v0 = ch.x >= 0 && ray_box<D>(b0, x, inv, 0.f, tmax) < INFINITY;
-        bool v1 = ch.z >= 0 && ray_box<D>(b1, x, inv, 0.f, tmax) < INFINITY;
-        if (v0 && ch.y > 0) {
-            for (int k = ch.x; k < ch.x + ch.y; ++k) {
-                if (k == skip) continue;
-                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                const float t = pr.ray(ry);
-                if (t > tau && t < tmax) return false;
-            }
-            v0 = false;
+    Box<D> b0, b1;
+    int4 ch;
+    load_node_boxes<D>((const NodeType*)b.nodes, q.t.node, b0, b1, ch);
+    stat_node(s);
+    const float e0 = ch.x >= 0 ? ray_box<D>(b0, x, q.inv, -back, q.t.best) : INFINITY;
+    const float e1 = ch.z >= 0 ? ray_box<D>(b1, x, q.inv, -back, q.t.best) : INFINITY;
+    bool v0 = e0 < INFINITY, v1 = e1 < INFINITY;
+    if (v0 && ch.y > 0) {
+        for (int k = ch.x; k < ch.x + ch.y; ++k) {
+            if (k == skip) continue;
+            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+            const float t = pr.ray(ry);
+            if (t < q.t.best && (t > tau || (t > -back && exits<D>(b, k, nu)))) { q.t.best = t; q.t.prim = k; }
         }
-        if (v1 && ch.w > 0) {
-            for (int k = ch.z; k < ch.z + ch.w; ++k) {
-                if (k == skip) continue;
-                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                const float t = pr.ray(ry);
-                if (t > tau && t < tmax) return false;
-            }
-            v1 = false;
-        }
-        if (v0 && v1) { st.put(sp++, ch.z, 0.f); node = ch.x; continue; }
-        if (v0) { node = ch.x; continue; }
-        if (v1) { node = ch.z; continue; }
-        if (sp == 0) break;
-        node = (int)st.get(--sp).x;
+        v0 = false;
     }
-    return true;
+    if (v1 && ch.w > 0) {
+        for (int k = ch.z; k < ch.z + ch.w; ++k) {
+            if (k == skip) continue;
+            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+            const float t = pr.ray(ry);
+            if (t < q.t.best && (t > tau || (t > -back && exits<D>(b, k, nu)))) { q.t.best = t; q.t.prim = k; }
+        }
+        v1 = false;
+    }
+    v0 = v0 && e0 < q.t.best;
+    v1 = v1 && e1 < q.t.best;
+    return !trav_next(v0, v1, e0, e1, ch, q.t.best, q.t, st);
+}
+
+// ---- visibility: does a Neumann primitive other than `skip` cross the ray
+// x + t nu (unit nu) at t in (t_lo, t_hi)?  Any-hit: finishes at the first
+// blocker, with q.t.prim >= 0; q.t.best holds t_hi.
+template <int D, class S>
+__device__ __forceinline__ bool visible_neumann_step(const DevBvh& b, const float* x, const float* nu, float t_lo,
+                                                     int skip, RayTrav<D>& q, const LdsStack& st, S* s)
+{
+    if (q.t.node < 0) return true;
+    using NodeType = typename NodeT<D>::type;
+    const RaySetup<D> ry(x, nu);
+    const float tmax = q.t.best;
+    Box<D> b0, b1;
+    int4 ch;
+    load_node_boxes<D>((const NodeType*)b.nodes, q.t.node, b0, b1, ch);
+    stat_node(s);
+    bool v0 = ch.x >= 0 && ray_box<D>(b0, x, q.inv, 0.f, tmax) < INFINITY;
+    bool v1 = ch.z >= 0 && ray_box<D>(b1, x, q.inv, 0.f, tmax) < INFINITY;
+    if (v0 && ch.y > 0) {
+        for (int k = ch.x; k < ch.x + ch.y; ++k) {
+            if (k == skip) continue;
+            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+            const float t = pr.ray(ry);
+            if (t > t_lo && t < tmax) { q.t.prim = k; q.t.node = -1; return true; }
+        }
+        v0 = false;
+    }
+    if (v1 && ch.w > 0) {
+        for (int k = ch.z; k < ch.z + ch.w; ++k) {
+            if (k == skip) continue;
+            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+            const float t = pr.ray(ry);
+            if (t > t_lo && t < tmax) { q.t.prim = k; q.t.node = -1; return true; }
+        }
+        v1 = false;
+    }
+    return !trav_next(v0, v1, 0.f, 0.f, ch, INFINITY, q.t, st);
 }
 
 // ----------------------------------------------------------------- Neumann sample
@@ -624,64 +603,138 @@ __device__ bool visible_neumann(const DevBvh& b, const float* x, const float* nu
 // child with probability proportional to its subtree measure (children whose
 // box misses the ball get weight 0), then a primitive of the leaf in
 // proportion to its measure among the leaf primitives meeting the ball.
-// Returns the primitive (or -1) and the probability of having chosen it.
+// State: node (-1 when finished), the running uniform u, the probability of
+// the path so far, and the result (prim, prob).
+struct SampleTrav {
+    int node;
+    float u, P;
+    int prim;
+    float prob;
+};
+
+__device__ __forceinline__ void sample_begin(const DevBvh& b, float u, SampleTrav& q)
+{
+    q.node = b.n_nodes > 0 ? 0 : -1;
+    q.u = u;
+    q.P = 1.f;
+    q.prim = -1;
+    q.prob = 0.f;
+}
+
+template <int D, class S>
+__device__ __forceinline__ bool sample_neumann_step(const DevBvh& b, const float* x, float r, SampleTrav& q, S* s)
+{
+    if (q.node < 0) return true;
+    using NodeType = typename NodeT<D>::type;
+    const float r2 = r * r;
+    Box<D> b0, b1;
+    int4 ch;
+    float4 a0, a1;
+    load_node((const NodeType*)b.nodes, q.node, b0, b1, ch, a0, a1);
+    stat_node(s);
+    const float w0 = box_dist2<D>(b0, x) < r2 ? a0.x : 0.f;
+    const float w1 = box_dist2<D>(b1, x) < r2 ? a1.x : 0.f;
+    const float W = w0 + w1;
+    if (!(W > 0.f)) { q.node = -1; return true; }
+    const float p0 = w0 / W;
+    int c, n;
+    float u = q.u;
+    if (u < p0) {
+        c = ch.x; n = ch.y; q.P *= p0;
+        u = u / p0;
+    } else {
+        c = ch.z; n = ch.w; q.P *= (1.f - p0);
+        u = (u - p0) / (1.f - p0);
+    }
+    u = fminf(fmaxf(u, 0.f), 0.99999994f);
+    q.u = u;
+    if (n == 0) { q.node = c; return false; }
+    // leaf: measure-weighted choice among primitives meeting the ball
+    q.node = -1;
+    float tot = 0.f;
+    for (int k = c; k < c + n; ++k) {
+        Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+        float z[D];
+        if (pr.closest(x, z) < r2) tot += b.pextra[k].w;
+    }
+    if (!(tot > 0.f)) return true;
+    const float target = u * tot;
+    float acc = 0.f;
+    int sel = -1;
+    float wsel = 0.f;
+    for (int k = c; k < c + n; ++k) {
+        Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+        float z[D];
+        if (!(pr.closest(x, z) < r2)) continue;
+        const float w = b.pextra[k].w;
+        sel = k; wsel = w;
+        acc += w;
+        if (target < acc) break;
+    }
+    q.prim = sel;
+    q.prob = q.P * (wsel / tot);
+    return true;
+}
+
+// ----------------------------------------------------------------- run to completion
+
+// Squared distance to the closest Dirichlet point (best2 on entry bounds the
+// search), the point itself and its internal primitive (-1 if none found).
+template <int D, class S = NoStat>
+__device__ float closest_dirichlet(const DevBvh& b, const float* x, float best2, float* xbar, int* prim_out,
+                                   const LdsStack& st, S* s = nullptr)
+{
+    Trav q;
+    trav_begin(b, best2, q);
+    while (!closest_dirichlet_step<D>(b, x, q, st, s)) {}
+    *prim_out = q.prim;
+    if (q.prim >= 0) {
+        Prim<D> pr;
+        pr.load(b.prims, q.prim);
+        pr.closest(x, xbar);
+    }
+    return q.best;
+}
+
+template <int D, class S = NoStat>
+__device__ float closest_silhouette(const DevBvh& b, const float* x, float best2, int onp, const LdsStack& st,
+                                    S* s = nullptr)
+{
+    Trav q;
+    trav_begin(b, best2, q);
+    while (!closest_silhouette_step<D>(b, x, onp, q, st, s)) {}
+    return q.best;
+}
+
+template <int D, class S = NoStat>
+__device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, float tmax, float tau, int skip,
+                             int* hit, const LdsStack& st, S* s = nullptr, float back = 0.f)
+{
+    RayTrav<D> q;
+    ray_begin<D>(b, nu, tmax, q);
+    while (!ray_neumann_step<D>(b, x, nu, tau, back, skip, q, st, s)) {}
+    *hit = q.t.prim;
+    return q.t.prim >= 0 ? q.t.best : INFINITY;
+}
+
+template <int D, class S = NoStat>
+__device__ bool visible_neumann(const DevBvh& b, const float* x, const float* nu, float t_lo, float t_hi, int skip,
+                                const LdsStack& st, S* s = nullptr)
+{
+    RayTrav<D> q;
+    ray_begin<D>(b, nu, t_hi, q);
+    while (!visible_neumann_step<D>(b, x, nu, t_lo, skip, q, st, s)) {}
+    return q.t.prim < 0;
+}
+
 template <int D, class S = NoStat>
 __device__ int sample_neumann(const DevBvh& b, const float* x, float r, float u, float* prob, S* s = nullptr)
 {
-    using NodeType = typename NodeT<D>::type;
-    const NodeType* nodes = (const NodeType*)b.nodes;
-    *prob = 0.f;
-    if (b.n_nodes == 0) return -1;
-    const float r2 = r * r;
-    float P = 1.f;
-    int node = 0;
-    for (;;) {
-        Box<D> b0, b1;
-        int4 ch;
-        float4 a0, a1;
-        load_node(nodes, node, b0, b1, ch, a0, a1);
-        stat_node(s);
-        const float w0 = box_dist2<D>(b0, x) < r2 ? a0.x : 0.f;
-        const float w1 = box_dist2<D>(b1, x) < r2 ? a1.x : 0.f;
-        const float W = w0 + w1;
-        if (!(W > 0.f)) return -1;
-        const float p0 = w0 / W;
-        int c, n;
-        if (u < p0) {
-            c = ch.x; n = ch.y; P *= p0;
-            u = u / p0;
-        } else {
-            c = ch.z; n = ch.w; P *= (1.f - p0);
-            u = (u - p0) / (1.f - p0);
-        }
-        u = fminf(fmaxf(u, 0.f), 0.99999994f);
-        if (n > 0) {
-            // leaf: measure-weighted choice among primitives meeting the ball
-            float tot = 0.f;
-            for (int k = c; k < c + n; ++k) {
-                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                float z[D];
-                if (pr.closest(x, z) < r2) tot += b.pextra[k].w;
-            }
-            if (!(tot > 0.f)) return -1;
-            const float target = u * tot;
-            float acc = 0.f;
-            int sel = -1;
-            float wsel = 0.f;
-            for (int k = c; k < c + n; ++k) {
-                Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-                float z[D];
-                if (!(pr.closest(x, z) < r2)) continue;
-                const float w = b.pextra[k].w;
-                sel = k; wsel = w;
-                acc += w;
-                if (target < acc) break;
-            }
-            *prob = P * (wsel / tot);
-            return sel;
-        }
-        node = c;
-    }
+    SampleTrav q;
+    sample_begin(b, u, q);
+    while (!sample_neumann_step<D>(b, x, r, q, s)) {}
+    *prob = q.prob;
+    return q.prim;
 }
 
 }  // namespace wost

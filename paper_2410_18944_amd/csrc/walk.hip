@@ -43,6 +43,11 @@ struct WalkParams {
     unsigned long long* cost;       // 12 traversal counters (statistics variant only)
     GuideDev guide;
     RecDev rec;
+    uint32_t* pool;                 // walk pools: PoolField<D>::WORDS arrays of pool_total words
+    int64_t pool_total;             // slots over all waves (grid * pool_n)
+    int32_t pool_n;                 // slots per wave (multiple of 64)
+    int32_t* lists;                 // 4 work lists of pool_n entries per wave
+    int32_t refill_batch;           // finished lanes that wait for a joint refill
 };
 
 __device__ __forceinline__ uint32_t lane_prefix(uint64_t mask)
@@ -81,299 +86,643 @@ static inline size_t walk_lds_bytes(bool guided, int max_depth, int out_stride)
     return stack > gout ? stack : gout;
 }
 
+// ---------------------------------------------------------------- walk pool
+//
+// Each wave owns N walk slots, kept as structure of arrays in the caller's
+// workspace.  A round moves
+// every live walk of the pool one star forward, phase by phase: closest
+// Dirichlet point, closest silhouette (star radius, uniform direction), guide
+// evaluation and guided direction in full 64-walk chunks, Neumann sample and
+// its visibility, source point and its visibility, first hit, then the step
+// update.  Inside a traversal phase a lane whose query has finished takes the
+// next walk of that phase's list at once, so the wave does not wait for its
+// slowest lane; lanes of a phase all run the same query code.
+
+enum : int { ST_EMPTY = 0, ST_ACTIVE = 1, ST_STEP = 2, ST_DONE = 3 };
+
+template <int D>
+struct PoolField {
+    static constexpr int X = 0, NIN = D, NU = 2 * D, Z = 3 * D, Y = 4 * D;
+    static constexpr int T = 5 * D, ACC = T + 1, DD = T + 2, R = T + 3, W = T + 4, PMIS = T + 5, CON = T + 6,
+                         NVAL = T + 7, SVAL = T + 8, TH = T + 9, K = T + 10, ONP = T + 11, HIT = T + 12,
+                         STAT = T + 13, WLO = T + 14, WHI = T + 15;
+    static constexpr int WORDS = T + 16;
+};
+
+// Field-major storage (field f of global slot g at pool[f * total + g]):
+// the finalize pass and the start of every phase touch consecutive slots, so
+// a field access of the wave is one contiguous 256-byte block.  32-bit word
+// offsets (fields * slots < 2^32, checked on the host) keep each access one
+// VGPR offset from a scalar base.
+template <int D>
+struct PoolView {
+    uint32_t* base;
+    uint32_t total;
+    __device__ __forceinline__ float& f(int fld, uint32_t g) const { return ((float*)base)[(uint32_t)fld * total + g]; }
+    __device__ __forceinline__ int32_t& i(int fld, uint32_t g) const { return ((int32_t*)base)[(uint32_t)fld * total + g]; }
+    __device__ __forceinline__ uint32_t& u(int fld, uint32_t g) const { return base[(uint32_t)fld * total + g]; }
+    __device__ __forceinline__ uint64_t wid(uint32_t g) const
+    {
+        return (uint64_t)u(PoolField<D>::WLO, g) | ((uint64_t)u(PoolField<D>::WHI, g) << 32);
+    }
+};
+
+__device__ __forceinline__ uint64_t wave_uniform_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ Stream walk_stream(const WalkParams& P, uint64_t wid)
+{
+    Stream rs;
+    rs.k0 = P.key0;
+    rs.k1 = P.key1;
+    const uint64_t p = wid / (uint64_t)P.wpp;
+    rs.p = (uint32_t)p;
+    rs.j = (uint32_t)(P.walk_offset + (wid - p * (uint64_t)P.wpp));
+    return rs;
+}
+
+// memory written by one lane of the wave becomes visible to the others
+__device__ __forceinline__ void wave_sync()
+{
+    __threadfence_block();
+    __syncthreads();
+}
+
+// Lanes that have finished their query wait until at least this many are
+// waiting (or no lane is still traversing) before they store results and
+// take new work together: finishing and refilling is far more code than one
+// traversal iteration, and run for a handful of lanes at a time it would cost
+// nearly as much as for all 64.
+static int g_refill_batch = 16;
+
+// One traversal phase over list[0, n) with refill from the list: init(slot)
+// loads a walk's query, step() advances it by one node and returns true when
+// done, finish(slot) stores the result and returns true to append the slot
+// to `out` (if given).  `out_n` and the loop counters stay wave-uniform.
+template <class Init, class Step, class Finish>
+__device__ __forceinline__ void run_phase(const int32_t* list, int n, int32_t* out, int& out_n, int lane, int batch,
+                                          unsigned long long& iters, Init&& init, Step&& step, Finish&& finish)
+{
+    int slot = -1;
+    bool waiting = false;
+    int next = n < kWave ? n : kWave;
+    if (lane < n) {
+        slot = list[lane];
+        init(slot);
+    }
+    for (;;) {
+        const bool running = slot >= 0 && !waiting;
+        const uint64_t run_m = __ballot(running);
+        const uint64_t wait_m = __ballot(waiting);
+        if (run_m == 0 && wait_m == 0) break;
+        if (run_m) {
+            ++iters;
+            if (running) waiting = step();
+        }
+        const uint64_t w2 = __ballot(waiting);
+        if (w2 == 0) continue;
+        const uint64_t r2 = __ballot(slot >= 0 && !waiting);
+        if (__popcll(w2) < batch && r2 != 0) continue;
+        // finish and refill every waiting lane
+        bool app = false;
+        if (waiting) app = finish(slot);
+        if (out) {
+            const uint64_t m = __ballot(app);
+            if (m) {
+                if (app) out[out_n + (int)lane_prefix(m)] = slot;
+                out_n += __popcll(m);
+            }
+        }
+        if (waiting) {
+            const int i = next + (int)lane_prefix(w2);
+            slot = i < n ? list[i] : -1;
+            waiting = false;
+            if (slot >= 0) init(slot);
+        }
+        next += __popcll(w2);
+    }
+}
+
 template <int D, bool GUIDED, bool STATS>
 __device__ __forceinline__ void walk_body(const WalkParams& P)
 {
+    using F = PoolField<D>;
     // per-query traversal counters (empty structs unless STATS):
     // 0 closest Dirichlet, 1 silhouette, 2 Neumann sample, 3 Neumann
     // visibility, 4 source visibility, 5 first hit
     using S = typename std::conditional<STATS, Stat, NoStat>::type;
     S sq[6];
+    unsigned long long witer[6] = {0ull, 0ull, 0ull, 0ull, 0ull, 0ull};
     extern __shared__ uint2 s_lds[];
     const int lane = threadIdx.x;
     const LdsStack st{&s_lds[lane]};
     float* const s_out = (float*)s_lds;
     const int out_stride = guide_out_stride(P.guide);
     const DevGeom& G = P.geom;
-
-    bool active = false;
-    uint64_t wid = 0;
-    Stream rs;
-    rs.k0 = P.key0;
-    rs.k1 = P.key1;
-    rs.p = 0;
-    rs.j = 0;
-    int k = 0, onp = -1;
-    float x[D], nin[D], T = 1.f, acc = 0.f;
-#pragma unroll
-    for (int i = 0; i < D; ++i) { x[i] = 0.f; nin[i] = 0.f; }
-    bool exhausted = false;
-    // the wave's private pool of walk ids [pool_next, pool_end), refilled one
-    // chunk at a time from the global counter (one atomic per chunk)
-    uint64_t pool_next = 0, pool_end = 0;
-    unsigned long long n_steps = 0, n_walks = 0, n_trunc = 0, n_rr = 0, n_bad = 0, n_rec = 0, n_drop = 0;
+    const int N = P.pool_n;
+    const uint32_t base = (uint32_t)blockIdx.x * (uint32_t)N;
+    const PoolView<D> pv{P.pool, (uint32_t)P.pool_total};
+    int32_t* const L_act = P.lists + (int64_t)blockIdx.x * 4 * N;
+    int32_t* const L_step = L_act + N;
+    int32_t* const L_vis = L_act + 2 * N;
+    int32_t* const L_svis = L_act + 3 * N;
     const bool has_h = P.h.kind != WOST_FIELD_ZERO;
     const bool has_f = P.f.kind != WOST_FIELD_ZERO;
     const float area = D == 2 ? 2.f * kPi : 4.f * kPi;
+    uint32_t n_steps = 0, n_walks = 0, n_trunc = 0, n_rr = 0, n_bad = 0, n_rec = 0, n_drop = 0;
+    bool exhausted = false;
+    // the wave's private range of walk ids [pool_next, pool_end), refilled one
+    // chunk at a time from the global counter (one atomic per chunk)
+    uint64_t pool_next = 0, pool_end = 0;
+    int dummy_n = 0;
+    const int batch = P.refill_batch;
+
+    for (int c = lane; c < N; c += kWave) pv.i(F::STAT, base + c) = ST_EMPTY;
+    wave_sync();
 
     for (;;) {
-        // ---- refill free lanes (wave-uniform control flow)
-        if (!exhausted) {
-            const uint64_t freem = __ballot(!active);
-            if (freem) {
-                const uint32_t cnt = (uint32_t)__popcll(freem);
-                if (pool_next >= pool_end) {
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(P.work, (unsigned long long)P.chunk);
-                    const uint32_t blo = __shfl((uint32_t)base, 0), bhi = __shfl((uint32_t)(base >> 32), 0);
-                    base = ((unsigned long long)bhi << 32) | blo;
-                    pool_next = base;
-                    pool_end = base + P.chunk < P.n_walks ? base + P.chunk : P.n_walks;
-                    if (base >= P.n_walks) exhausted = true;
-                }
-                const uint64_t avail = pool_end > pool_next ? pool_end - pool_next : 0;
-                if (!active && !exhausted) {
-                    const uint64_t slot = lane_prefix(freem);
-                    const uint64_t id = pool_next + slot;
-                    if (slot < avail) {
-                        active = true;
-                        wid = id;
-                        const uint64_t p = id / (uint64_t)P.wpp;
-                        const uint64_t j = id - p * (uint64_t)P.wpp;
-                        rs.p = (uint32_t)p;
-                        rs.j = (uint32_t)(P.walk_offset + j);
+        // ---- step update of last round's walks, retirement, refill
+        int n_act = 0;
+        for (int c0 = 0; c0 < N; c0 += kWave) {
+            const int li = c0 + lane;
+            const uint32_t g = base + li;
+            int stt = pv.i(F::STAT, g);
+            bool do_rec = false;
+            float rec_x[D], rec_nin[D], rec_nu[D], rec_pmis = 0.f, rec_prefix = 0.f, rec_tnext = 0.f;
+            uint64_t wid = 0;
+            if (stt == ST_STEP) {
+                wid = pv.wid(g);
+                float x[D], nin[D], nu[D];
 #pragma unroll
-                        for (int i = 0; i < D; ++i) { x[i] = P.pts[p * D + i]; nin[i] = 0.f; }
-                        k = 0; onp = -1; T = 1.f; acc = 0.f;
+                for (int i = 0; i < D; ++i) {
+                    x[i] = pv.f(F::X + i, g);
+                    nin[i] = pv.f(F::NIN + i, g);
+                    nu[i] = pv.f(F::NU + i, g);
+                }
+                int onp = pv.i(F::ONP, g);
+                const bool onN = onp >= 0;
+                float T = pv.f(F::T, g), acc = pv.f(F::ACC, g);
+                int k = pv.i(F::K, g);
+                const float r = pv.f(F::R, g), th = pv.f(F::TH, g), w = pv.f(F::W, g);
+                const int hp = pv.i(F::HIT, g);
+                acc = fmaf(T, pv.f(F::CON, g), acc);
+#pragma unroll
+                for (int i = 0; i < D; ++i) { rec_x[i] = x[i]; rec_nin[i] = onN ? nin[i] : 0.f; rec_nu[i] = nu[i]; }
+                float xo[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) xo[i] = onN ? fmaf(G.tau, nin[i], x[i]) : x[i];
+                if (hp >= 0) {
+                    // the walk's side of a Neumann primitive is the domain, so
+                    // its normal toward the walk is -n_out (a first hit seen
+                    // from inside is always an exit, nu . n_out > 0)
+                    const float4 ex = G.neu.pextra[hp];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        x[i] = fmaf(th, nu[i], xo[i]);
+                        nin[i] = -(i == 0 ? ex.x : (i == 1 ? ex.y : ex.z));
+                    }
+                    onp = hp;
+                } else {
+                    // the segment from the ray's origin to this point crosses
+                    // no boundary, so the walker stays inside; stepping from
+                    // x itself could leave the domain by up to tau along a
+                    // grazing ray
+#pragma unroll
+                    for (int i = 0; i < D; ++i) x[i] = fmaf(r, nu[i], xo[i]);
+                    onp = -1;
+                }
+                T *= w;
+                ++k;
+                stt = ST_ACTIVE;
+                // Russian roulette for the next star (played with that step's word)
+                if (k >= P.rr_start) {
+                    const uint4 wr = walk_stream(P, wid).block((uint32_t)k, kBlkNeu);
+                    if (u01(wr.w) >= P.rr_q) { stt = ST_DONE; ++n_rr; }
+                    else T /= P.rr_q;
+                }
+#pragma unroll
+                for (int i = 0; i < D; ++i) { pv.f(F::X + i, g) = x[i]; pv.f(F::NIN + i, g) = nin[i]; }
+                pv.i(F::ONP, g) = onp;
+                pv.f(F::T, g) = T;
+                pv.f(F::ACC, g) = acc;
+                pv.i(F::K, g) = k;
+                rec_pmis = pv.f(F::PMIS, g);
+                rec_prefix = acc;
+                rec_tnext = T;
+                do_rec = GUIDED && P.rec.data != nullptr;
+            }
+            if (stt == ST_DONE) {
+                if (!do_rec) wid = pv.wid(g);
+                ++n_walks;
+                P.slot_value[wid] = pv.f(F::ACC, g);
+                if (P.slot_steps) P.slot_steps[wid] = pv.i(F::K, g);
+                stt = ST_EMPTY;
+            }
+            // ---- training record append (one atomic per chunk)
+            if constexpr (GUIDED) {
+                const uint64_t rm = __ballot(do_rec);
+                if (rm) {
+                    const uint32_t cnt = (uint32_t)__popcll(rm);
+                    const int leader = __ffsll((unsigned long long)rm) - 1;
+                    unsigned long long rb = 0;
+                    if (lane == leader) rb = atomicAdd(P.rec.count, (unsigned long long)cnt);
+                    const uint32_t blo = __shfl((uint32_t)rb, leader), bhi = __shfl((uint32_t)(rb >> 32), leader);
+                    rb = ((unsigned long long)bhi << 32) | blo;
+                    if (do_rec) {
+                        const uint64_t row = rb + lane_prefix(rm);
+                        if (row < (uint64_t)P.rec.capacity) {
+                            float* dst = P.rec.data + row;
+                            const int64_t C = P.rec.capacity;
+#pragma unroll
+                            for (int i = 0; i < D; ++i) {
+                                dst[(int64_t)i * C] = rec_x[i];
+                                dst[(int64_t)(D + i) * C] = rec_nu[i];
+                                dst[(int64_t)(2 * D + i) * C] = rec_nin[i];
+                            }
+                            dst[(int64_t)(3 * D) * C] = rec_pmis;
+                            dst[(int64_t)(3 * D + 1) * C] = rec_prefix;
+                            dst[(int64_t)(3 * D + 2) * C] = rec_tnext;
+                            dst[(int64_t)(3 * D + 3) * C] = __uint_as_float((uint32_t)wid);
+                            dst[(int64_t)(3 * D + 4) * C] = 0.f;
+                            ++n_rec;
+                        } else {
+                            ++n_drop;
+                        }
                     }
                 }
-                pool_next += cnt < avail ? cnt : avail;
             }
-        }
-        if (__ballot(active) == 0) break;
-        if constexpr (STATS) {
+            // ---- refill empty slots with new walks (wave-uniform control flow)
+            if (!exhausted) {
+                const uint64_t freem = __ballot(stt == ST_EMPTY);
+                if (freem) {
+                    const uint32_t cnt = (uint32_t)__popcll(freem);
+                    if (pool_next >= pool_end) {
+                        unsigned long long wb = 0;
+                        if (lane == 0) wb = atomicAdd(P.work, (unsigned long long)P.chunk);
+                        const uint32_t blo = __shfl((uint32_t)wb, 0), bhi = __shfl((uint32_t)(wb >> 32), 0);
+                        wb = wave_uniform_u64(((unsigned long long)bhi << 32) | blo);
+                        pool_next = wb;
+                        pool_end = wb + P.chunk < P.n_walks ? wb + P.chunk : P.n_walks;
+                        if (wb >= P.n_walks) exhausted = true;
+                    }
+                    const uint64_t avail = pool_end > pool_next ? pool_end - pool_next : 0;
+                    if (stt == ST_EMPTY && !exhausted) {
+                        const uint64_t rank = lane_prefix(freem);
+                        if (rank < avail) {
+                            const uint64_t id = pool_next + rank;
+                            const uint64_t p = id / (uint64_t)P.wpp;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) sq[q].step0 = sq[q].nodes;
-        }
-
-        // ---- phase A: closest Dirichlet point, epsilon-shell / step-cap termination
-        bool stepping = false, finish = false;
-        float dD = 0.f;
-        if (active) {
-            ++n_steps;
-            float xbar[D];
-            int dp;
-            const float d2 = closest_dirichlet<D>(G.dir, x, INFINITY, xbar, &dp, st, &sq[0]);
-            dD = sqrtf(d2);
-            if (dD <= P.eps || k >= P.max_steps) {
-                acc = fmaf(T, field_value<D>(P.g, xbar), acc);
-                finish = true;
-                if (!(dD <= P.eps)) ++n_trunc;
-            } else {
-                stepping = true;
+                            for (int i = 0; i < D; ++i) { pv.f(F::X + i, g) = P.pts[p * D + i]; pv.f(F::NIN + i, g) = 0.f; }
+                            pv.i(F::ONP, g) = -1;
+                            pv.f(F::T, g) = 1.f;
+                            pv.f(F::ACC, g) = 0.f;
+                            pv.i(F::K, g) = 0;
+                            pv.u(F::WLO, g) = (uint32_t)id;
+                            pv.u(F::WHI, g) = (uint32_t)(id >> 32);
+                            stt = ST_ACTIVE;
+                        }
+                    }
+                    pool_next = wave_uniform_u64(pool_next + (cnt < avail ? cnt : avail));
+                }
             }
+            pv.i(F::STAT, g) = stt;
+            const uint64_t am = __ballot(stt == ST_ACTIVE);
+            if (stt == ST_ACTIVE) L_act[n_act + (int)lane_prefix(am)] = li;
+            n_act += __popcll(am);
         }
-        const bool onN = onp >= 0;
-        const float inv_alpha = onN ? 2.f : 1.f;
+        if (n_act == 0 && exhausted) break;
+        wave_sync();
 
-        // ---- phase B+C: direction of the recursive term (guided: wave-wide
-        // network evaluation, then each lane draws from its own mixture)
-        float nu[D];
-        float w = 1.f, pmis = 1.f / area;
-        const uint4 wd = rs.block((uint32_t)k, kBlkDir);
+        // ---- closest Dirichlet point; epsilon-shell and step-cap termination
+        int n_step = 0;
+        {
+            float x[D];
+            Trav q;
+            run_phase(L_act, n_act, L_step, n_step, lane, batch, witer[0],
+                [&](int slot) {
+                    const uint32_t g = base + slot;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) x[i] = pv.f(F::X + i, g);
+                    trav_begin(G.dir, INFINITY, q);
+                },
+                [&]() { return closest_dirichlet_step<D>(G.dir, x, q, st, &sq[0]); },
+                [&](int slot) {
+                    const uint32_t g = base + slot;
+                    ++n_steps;
+                    const float dD = q.prim >= 0 ? sqrtf(q.best) : INFINITY;
+                    const int k = pv.i(F::K, g);
+                    if (dD <= P.eps || k >= P.max_steps) {
+                        float xbar[D];
+                        float gv = 0.f;
+                        if (q.prim >= 0) {
+                            Prim<D> pr;
+                            pr.load(G.dir.prims, q.prim);
+                            pr.closest(x, xbar);
+                            gv = field_value<D>(P.g, xbar);
+                        }
+                        pv.f(F::ACC, g) = fmaf(pv.f(F::T, g), gv, pv.f(F::ACC, g));
+                        pv.i(F::K, g) = k + 1;
+                        pv.i(F::STAT, g) = ST_DONE;
+                        if (!(dD <= P.eps)) ++n_trunc;
+                        return false;
+                    }
+                    pv.f(F::DD, g) = dD;
+                    pv.i(F::STAT, g) = ST_STEP;
+                    return true;
+                });
+        }
+        wave_sync();
+        if (n_step == 0) continue;
+
+        // ---- closest silhouette -> star radius; uniform direction
+        {
+            float x[D], dD = 0.f;
+            int onp = -1;
+            Trav q;
+            run_phase(L_step, n_step, (int32_t*)nullptr, dummy_n, lane, batch, witer[1],
+                [&](int slot) {
+                    const uint32_t g = base + slot;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) x[i] = pv.f(F::X + i, g);
+                    onp = pv.i(F::ONP, g);
+                    dD = pv.f(F::DD, g);
+                    trav_begin(G.sil, dD * dD, q);
+                },
+                [&]() { return closest_silhouette_step<D>(G.sil, x, onp, q, st, &sq[1]); },
+                [&](int slot) {
+                    const uint32_t g = base + slot;
+                    const float r = fmaxf(fminf(dD, sqrtf(q.best)), P.r_min);
+                    pv.f(F::R, g) = r;
+                    pv.f(F::CON, g) = 0.f;
+                    if constexpr (!GUIDED) {
+                        const Stream rs = walk_stream(P, pv.wid(g));
+                        const uint4 wd = rs.block((uint32_t)pv.i(F::K, g), kBlkDir);
+                        float nu[D];
+                        uniform_dir<D>(u01(wd.x), u01(wd.y), nu);
+                        if (onp >= 0) {
+                            float nin[D];
+#pragma unroll
+                            for (int i = 0; i < D; ++i) nin[i] = pv.f(F::NIN + i, g);
+                            const float c = dot<D>(nu, nin);
+                            if (c < 0.f) {
+#pragma unroll
+                                for (int i = 0; i < D; ++i) nu[i] = fmaf(-2.f * c, nin[i], nu[i]);
+                            }
+                        }
+#pragma unroll
+                        for (int i = 0; i < D; ++i) pv.f(F::NU + i, g) = nu[i];
+                        pv.f(F::W, g) = 1.f;
+                        pv.f(F::PMIS, g) = 1.f / area;
+                    }
+                    return false;
+                });
+        }
+        wave_sync();
+
+        // ---- guided direction: the network for 64 walks at a time on MFMA,
+        // then each lane draws from its own mixture
         if constexpr (GUIDED) {
-            const bool any_step = __ballot(stepping) != 0;
-            if (any_step) {
+            for (int c0 = 0; c0 < n_step; c0 += kWave) {
+                const int idx = c0 + lane;
+                const bool valid = idx < n_step;
+                const uint32_t g = base + L_step[valid ? idx : c0];
+                float x[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) x[i] = pv.f(F::X + i, g);
                 __syncthreads();
                 guide_forward_wave<D>(P.guide, x, s_out, lane, out_stride);
                 __syncthreads();
-                if (stepping) {
-                    guided_draw<D>(P.guide, s_out + lane * out_stride, rs, (uint32_t)k, wd, onN, nin, nu, &pmis);
-                    w = inv_alpha / (area * pmis);
-                    if (!(w >= 0.f && w < INFINITY)) { ++n_bad; w = 0.f; }
-                }
-                __syncthreads();
-            }
-        } else if (stepping) {
-            uniform_dir<D>(u01(wd.x), u01(wd.y), nu);
-            if (onN) {
-                const float c = dot<D>(nu, nin);
-                if (c < 0.f) {
+                if (valid) {
+                    const int onp = pv.i(F::ONP, g);
+                    const bool onN = onp >= 0;
+                    float nin[D], nu[D], pmis = 1.f / area;
 #pragma unroll
-                    for (int i = 0; i < D; ++i) nu[i] = fmaf(-2.f * c, nin[i], nu[i]);
+                    for (int i = 0; i < D; ++i) nin[i] = pv.f(F::NIN + i, g);
+                    const int k = pv.i(F::K, g);
+                    const Stream rs = walk_stream(P, pv.wid(g));
+                    const uint4 wd = rs.block((uint32_t)k, kBlkDir);
+                    guided_draw<D>(P.guide, s_out + lane * out_stride, rs, (uint32_t)k, wd, onN, nin, nu, &pmis);
+                    float w = (onN ? 2.f : 1.f) / (area * pmis);
+                    if (!(w >= 0.f && w < INFINITY)) { ++n_bad; w = 0.f; }
+#pragma unroll
+                    for (int i = 0; i < D; ++i) pv.f(F::NU + i, g) = nu[i];
+                    pv.f(F::W, g) = w;
+                    pv.f(F::PMIS, g) = pmis;
                 }
             }
+            wave_sync();
         }
 
-        // ---- phase D: star radius, Neumann and source terms, first hit
-        bool do_rec = false;
-        float rec_x[D], rec_nin[D], rec_prefix = 0.f, rec_tnext = 0.f;
-        if (stepping) {
-            const float dS2 = closest_silhouette<D>(G.sil, x, dD * dD, onp, st, &sq[1]);
-            float r = fminf(dD, sqrtf(dS2));
-            r = fmaxf(r, P.r_min);
-            float contrib = 0.f;
-            // ray origin: a walker on the Neumann boundary shoots from a point
-            // tau inside along its normal, so every genuine crossing counts
-            float xo[D];
+        // ---- Neumann contribution: area-weighted point on a Neumann
+        // primitive meeting the ball, kept if it lies in the star
+        if (has_h) {
+            int n_vis = 0;
+            {
+                float x[D], r = 0.f, u1 = 0.f, u2 = 0.f;
+                SampleTrav q;
+                run_phase(L_step, n_step, L_vis, n_vis, lane, batch, witer[2],
+                    [&](int slot) {
+                        const uint32_t g = base + slot;
 #pragma unroll
-            for (int i = 0; i < D; ++i) xo[i] = onN ? fmaf(G.tau, nin[i], x[i]) : x[i];
-            // Neumann contribution: area-weighted point on a Neumann primitive
-            // meeting the ball, kept if it lies in the star
-            if (has_h) {
-                const uint4 wn = rs.block((uint32_t)k, kBlkNeu);
-                float prob;
-                const int q = sample_neumann<D>(G.neu, x, r, u01(wn.x), &prob, &sq[2]);
-                if (q >= 0 && prob > 0.f) {
-                    Prim<D> pr;
-                    pr.load(G.neu.prims, q);
-                    float z[D], dz[D], rho2 = 0.f;
-                    pr.point(u01(wn.y), u01(wn.z), z);
+                        for (int i = 0; i < D; ++i) x[i] = pv.f(F::X + i, g);
+                        r = pv.f(F::R, g);
+                        const uint4 wn = walk_stream(P, pv.wid(g)).block((uint32_t)pv.i(F::K, g), kBlkNeu);
+                        u1 = u01(wn.y);
+                        u2 = u01(wn.z);
+                        sample_begin(G.neu, u01(wn.x), q);
+                    },
+                    [&]() { return sample_neumann_step<D>(G.neu, x, r, q, &sq[2]); },
+                    [&](int slot) {
+                        if (!(q.prim >= 0 && q.prob > 0.f)) return false;
+                        const uint32_t g = base + slot;
+                        Prim<D> pr;
+                        pr.load(G.neu.prims, q.prim);
+                        float z[D], dz[D], rho2 = 0.f;
+                        pr.point(u1, u2, z);
 #pragma unroll
-                    for (int i = 0; i < D; ++i) { dz[i] = z[i] - x[i]; rho2 = fmaf(dz[i], dz[i], rho2); }
-                    const float rho = sqrtf(rho2);
-                    bool ok = rho < r && rho > 0.f;
-                    if (ok && onN && dot<D>(dz, nin) < -G.tau) ok = false;
-                    if (ok) {
-                        float dn[D], l2 = 0.f;
+                        for (int i = 0; i < D; ++i) { dz[i] = z[i] - x[i]; rho2 = fmaf(dz[i], dz[i], rho2); }
+                        const float rho = sqrtf(rho2);
+                        bool ok = rho < r && rho > 0.f;
+                        const int onp = pv.i(F::ONP, g);
+                        if (ok && onp >= 0) {
+                            float nin[D];
 #pragma unroll
-                        for (int i = 0; i < D; ++i) { dn[i] = z[i] - xo[i]; l2 = fmaf(dn[i], dn[i], l2); }
+                            for (int i = 0; i < D; ++i) nin[i] = pv.f(F::NIN + i, g);
+                            if (dot<D>(dz, nin) < -G.tau) ok = false;
+                        }
+                        if (!ok) return false;
+                        const float4 ex = G.neu.pextra[q.prim];
+                        const float no[3] = {ex.x, ex.y, ex.z};
+                        const float hv = neumann_value<D>(P.h, z, no);
+                        const float inv_alpha = onp >= 0 ? 2.f : 1.f;
+                        pv.f(F::NVAL, g) = green_ball<D>(r, rho) * hv * (ex.w / q.prob) * inv_alpha;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) pv.f(F::Z + i, g) = z[i];
+                        return true;
+                    });
+            }
+            wave_sync();
+            if (n_vis > 0) {
+                float xo[D], dn[D];
+                int onp = -1;
+                RayTrav<D> q;
+                run_phase(L_vis, n_vis, (int32_t*)nullptr, dummy_n, lane, batch, witer[3],
+                    [&](int slot) {
+                        const uint32_t g = base + slot;
+                        onp = pv.i(F::ONP, g);
+                        float l2 = 0.f;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            const float xi = pv.f(F::X + i, g);
+                            xo[i] = onp >= 0 ? fmaf(G.tau, pv.f(F::NIN + i, g), xi) : xi;
+                            dn[i] = pv.f(F::Z + i, g) - xo[i];
+                            l2 = fmaf(dn[i], dn[i], l2);
+                        }
                         const float len = sqrtf(l2);
 #pragma unroll
                         for (int i = 0; i < D; ++i) dn[i] /= len;
-                        ok = visible_neumann<D>(G.neu, xo, dn, 0.f, len - G.tau, onp, st, &sq[3]);
+                        ray_begin<D>(G.neu, dn, len - G.tau, q);
+                    },
+                    [&]() { return visible_neumann_step<D>(G.neu, xo, dn, 0.f, onp, q, st, &sq[3]); },
+                    [&](int slot) {
+                        if (q.t.prim < 0) {
+                            const uint32_t g = base + slot;
+                            pv.f(F::CON, g) += pv.f(F::NVAL, g);
+                        }
+                        return false;
+                    });
+                wave_sync();
+            }
+        }
+
+        // ---- source contribution: radius from the radial law of the ball's
+        // Green's function, uniform direction, kept if visible in the star
+        if (has_f) {
+            int n_svis = 0;
+            for (int c0 = 0; c0 < n_step; c0 += kWave) {
+                const int idx = c0 + lane;
+                bool app = false;
+                int slot = -1;
+                if (idx < n_step) {
+                    slot = L_step[idx];
+                    const uint32_t g = base + slot;
+                    const Stream rs = walk_stream(P, pv.wid(g));
+                    const uint32_t k = (uint32_t)pv.i(F::K, g);
+                    const uint4 a = rs.block(k, kBlkSrc0);
+                    const uint4 b = rs.block(k, kBlkSrc1);
+                    float sr;
+                    if (D == 2) {
+                        sr = sqrtf(u01(a.x) * u01(a.y));
+                    } else {
+                        const float u0 = u01(a.x), u1 = u01(a.y), u2 = u01(a.z);
+                        sr = fmaxf(fminf(u0, u1), fminf(fmaxf(u0, u1), u2));
+                    }
+                    float nu2[D];
+                    uniform_dir<D>(u01(a.w), u01(b.x), nu2);
+                    const int onp = pv.i(F::ONP, g);
+                    float nin[D], x[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) { nin[i] = pv.f(F::NIN + i, g); x[i] = pv.f(F::X + i, g); }
+                    bool ok = sr > 0.f;
+                    if (ok && onp >= 0 && dot<D>(nu2, nin) <= 0.f) ok = false;
+                    const float r = pv.f(F::R, g);
+                    float y[D], l2 = 0.f;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        y[i] = fmaf(sr * r, nu2[i], x[i]);
+                        const float xo = onp >= 0 ? fmaf(G.tau, nin[i], x[i]) : x[i];
+                        const float dy = y[i] - xo;
+                        l2 = fmaf(dy, dy, l2);
                     }
                     if (ok) {
-                        const float4 ex = G.neu.pextra[q];
-                        const float no[3] = {ex.x, ex.y, ex.z};
-                        const float hv = neumann_value<D>(P.h, z, no);
-                        contrib += green_ball<D>(r, rho) * hv * (ex.w / prob) * inv_alpha;
+                        const float sterm = (r * r / (2.f * D)) * field_value<D>(P.f, y) * (onp >= 0 ? 2.f : 1.f);
+                        if (sqrtf(l2) > 0.f) {
+                            pv.f(F::SVAL, g) = sterm;
+#pragma unroll
+                            for (int i = 0; i < D; ++i) pv.f(F::Y + i, g) = y[i];
+                            app = true;
+                        } else {
+                            pv.f(F::CON, g) -= sterm;
+                        }
                     }
                 }
-            }
-            // source contribution: radius from the radial law of the ball's
-            // Green's function, uniform direction, kept if visible in the star
-            if (has_f) {
-                const uint4 a = rs.block((uint32_t)k, kBlkSrc0);
-                const uint4 b = rs.block((uint32_t)k, kBlkSrc1);
-                float sr;
-                if (D == 2) {
-                    sr = sqrtf(u01(a.x) * u01(a.y));
-                } else {
-                    const float u0 = u01(a.x), u1 = u01(a.y), u2 = u01(a.z);
-                    sr = fmaxf(fminf(u0, u1), fminf(fmaxf(u0, u1), u2));
+                const uint64_t m = __ballot(app);
+                if (m) {
+                    if (app) L_svis[n_svis + (int)lane_prefix(m)] = slot;
+                    n_svis += __popcll(m);
                 }
-                float nu2[D];
-                uniform_dir<D>(u01(a.w), u01(b.x), nu2);
-                bool ok = sr > 0.f;
-                if (ok && onN && dot<D>(nu2, nin) <= 0.f) ok = false;
-                float y[D], dy[D], l2 = 0.f;
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    y[i] = fmaf(sr * r, nu2[i], x[i]);
-                    dy[i] = y[i] - xo[i];
-                    l2 = fmaf(dy[i], dy[i], l2);
-                }
-                const float len = sqrtf(l2);
-                if (ok && len > 0.f) {
-#pragma unroll
-                    for (int i = 0; i < D; ++i) dy[i] /= len;
-                    ok = visible_neumann<D>(G.neu, xo, dy, 0.f, len, onp, st, &sq[4]);
-                }
-                if (ok) contrib -= (r * r / (2.f * D)) * field_value<D>(P.f, y) * inv_alpha;
             }
-            acc = fmaf(T, contrib, acc);
-#pragma unroll
-            for (int i = 0; i < D; ++i) { rec_x[i] = x[i]; rec_nin[i] = onN ? nin[i] : 0.f; }
-            // first hit inside the star
-            int hp;
-            // the search runs to r + tau, so a boundary point at distance r
-            // (a silhouette point straight ahead) puts the walker on the
-            // boundary, and exits up to tau behind the origin count (the
-            // origin is then on the boundary up to rounding)
-            const float t = ray_neumann<D>(G.neu, xo, nu, r + G.tau, 0.f, onp, &hp, st, &sq[5], G.tau);
-            if (hp >= 0) {
-#pragma unroll
-                for (int i = 0; i < D; ++i) x[i] = fmaf(t, nu[i], xo[i]);
-                // the walk's side of a Neumann primitive is the domain, so its
-                // normal toward the walk is -n_out (a first hit seen from
-                // inside is always an exit, nu . n_out > 0)
-                const float4 ex = G.neu.pextra[hp];
-#pragma unroll
-                for (int i = 0; i < D; ++i) nin[i] = -(i == 0 ? ex.x : (i == 1 ? ex.y : ex.z));
-                onp = hp;
-            } else {
-                // the segment from the ray's origin to this point crosses no
-                // boundary, so the walker stays inside; stepping from x itself
-                // could leave the domain by up to tau along a grazing ray
-#pragma unroll
-                for (int i = 0; i < D; ++i) x[i] = fmaf(r, nu[i], xo[i]);
-                onp = -1;
-            }
-            T *= w;
-            ++k;
-            // Russian roulette for the next star (played with that step's word)
-            if (k >= P.rr_start) {
-                const uint4 wr = rs.block((uint32_t)k, kBlkNeu);
-                if (u01(wr.w) >= P.rr_q) { finish = true; ++n_rr; }
-                else T /= P.rr_q;
-            }
-            rec_prefix = acc;
-            rec_tnext = T;
-            do_rec = GUIDED && P.rec.data != nullptr;
-        }
-
-        // wave-level iterations of each query this step: the wave runs a
-        // traversal loop for as long as its slowest lane
-        if constexpr (STATS) {
-#pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                const uint32_t m = wave_max_u32(sq[q].nodes - sq[q].step0);
-                if (lane == 0) sq[q].witer += m;
-            }
-        }
-
-        // ---- phase E: training record append (one atomic per wave)
-        if constexpr (GUIDED) {
-            const uint64_t rm = __ballot(do_rec);
-            if (rm) {
-                const uint32_t cnt = (uint32_t)__popcll(rm);
-                const int leader = __ffsll((unsigned long long)rm) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(P.rec.count, (unsigned long long)cnt);
-                const uint32_t blo = __shfl((uint32_t)base, leader), bhi = __shfl((uint32_t)(base >> 32), leader);
-                base = ((unsigned long long)bhi << 32) | blo;
-                if (do_rec) {
-                    const uint64_t row = base + lane_prefix(rm);
-                    if (row < (uint64_t)P.rec.capacity) {
-                        float* dst = P.rec.data + row;
-                        const int64_t C = P.rec.capacity;
+            wave_sync();
+            if (n_svis > 0) {
+                float xo[D], dy[D];
+                int onp = -1;
+                RayTrav<D> q;
+                run_phase(L_svis, n_svis, (int32_t*)nullptr, dummy_n, lane, batch, witer[4],
+                    [&](int slot) {
+                        const uint32_t g = base + slot;
+                        onp = pv.i(F::ONP, g);
+                        float l2 = 0.f;
 #pragma unroll
                         for (int i = 0; i < D; ++i) {
-                            dst[(int64_t)i * C] = rec_x[i];
-                            dst[(int64_t)(D + i) * C] = nu[i];
-                            dst[(int64_t)(2 * D + i) * C] = rec_nin[i];
+                            const float xi = pv.f(F::X + i, g);
+                            xo[i] = onp >= 0 ? fmaf(G.tau, pv.f(F::NIN + i, g), xi) : xi;
+                            dy[i] = pv.f(F::Y + i, g) - xo[i];
+                            l2 = fmaf(dy[i], dy[i], l2);
                         }
-                        dst[(int64_t)(3 * D) * C] = pmis;
-                        dst[(int64_t)(3 * D + 1) * C] = rec_prefix;
-                        dst[(int64_t)(3 * D + 2) * C] = rec_tnext;
-                        dst[(int64_t)(3 * D + 3) * C] = __uint_as_float((uint32_t)wid);
-                        dst[(int64_t)(3 * D + 4) * C] = 0.f;
-                        ++n_rec;
-                    } else {
-                        ++n_drop;
-                    }
-                }
+                        const float len = sqrtf(l2);
+#pragma unroll
+                        for (int i = 0; i < D; ++i) dy[i] /= len;
+                        ray_begin<D>(G.neu, dy, len, q);
+                    },
+                    [&]() { return visible_neumann_step<D>(G.neu, xo, dy, 0.f, onp, q, st, &sq[4]); },
+                    [&](int slot) {
+                        if (q.t.prim < 0) {
+                            const uint32_t g = base + slot;
+                            pv.f(F::CON, g) -= pv.f(F::SVAL, g);
+                        }
+                        return false;
+                    });
+                wave_sync();
             }
         }
 
-        if (finish) {
-            ++n_walks;
-            P.slot_value[wid] = acc;
-            if (P.slot_steps) P.slot_steps[wid] = k + (stepping ? 0 : 1);
-            active = false;
+        // ---- first hit inside the star
+        {
+            float xo[D], nu[D];
+            int onp = -1;
+            RayTrav<D> q;
+            run_phase(L_step, n_step, (int32_t*)nullptr, dummy_n, lane, batch, witer[5],
+                [&](int slot) {
+                    const uint32_t g = base + slot;
+                    onp = pv.i(F::ONP, g);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const float xi = pv.f(F::X + i, g);
+                        xo[i] = onp >= 0 ? fmaf(G.tau, pv.f(F::NIN + i, g), xi) : xi;
+                        nu[i] = pv.f(F::NU + i, g);
+                    }
+                    // the search runs to r + tau, so a boundary point at
+                    // distance r (a silhouette point straight ahead) puts the
+                    // walker on the boundary, and exits up to tau behind the
+                    // origin count (the origin is then on the boundary up to
+                    // rounding)
+                    ray_begin<D>(G.neu, nu, pv.f(F::R, g) + G.tau, q);
+                },
+                [&]() { return ray_neumann_step<D>(G.neu, xo, nu, 0.f, G.tau, onp, q, st, &sq[5]); },
+                [&](int slot) {
+                    const uint32_t g = base + slot;
+                    pv.f(F::TH, g) = q.t.prim >= 0 ? q.t.best : INFINITY;
+                    pv.i(F::HIT, g) = q.t.prim;
+                    return false;
+                });
         }
+        wave_sync();
     }
+
     // ---- statistics: one atomic per wave and counter
     if constexpr (STATS) {
 #pragma unroll
@@ -382,11 +731,11 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             if (lane == 0) {
                 atomicAdd(P.cost + 2 * q, a);
                 atomicAdd(P.cost + 2 * q + 1, b);
-                atomicAdd(P.cost + 12 + q, sq[q].witer);
+                atomicAdd(P.cost + 12 + q, witer[q]);
             }
         }
     }
-    const unsigned long long vals[7] = {n_steps, n_walks, n_trunc, n_rr, n_bad, n_rec, n_drop};
+    const uint32_t vals[7] = {n_steps, n_walks, n_trunc, n_rr, n_bad, n_rec, n_drop};
 #pragma unroll
     for (int i = 0; i < 7; ++i) {
         const unsigned long long sm = wave_sum_u64(vals[i]);
@@ -524,10 +873,52 @@ static bool copy_field(const wost_field& in, int dim, FieldDev& out, const char*
 
 using namespace wost;
 
+static int g_pool_n = 512;   // walk slots per wave
+
+static inline int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
+static inline int pool_words(int dim) { return dim == 2 ? PoolField<2>::WORDS : PoolField<3>::WORDS; }
+
+// Slots per wave for a launch of `grid` waves: enough to hold the launch's
+// walks at once, at most g_pool_n, a multiple of 64.
+static inline int pool_slots(uint64_t n_walks, int grid)
+{
+    const uint64_t per = (n_walks + (uint64_t)grid - 1) / (uint64_t)grid;
+    const uint64_t n64 = (per + 63) / 64 * 64;
+    return (int)std::max<uint64_t>(64, std::min<uint64_t>(n64, (uint64_t)g_pool_n));
+}
+
+// Upper bound of the pool slots of any launch (grid <= 32 waves per CU and
+// grid <= ceil(walks / 64)): grid * pool_slots <= walks + 64 grid + 64.
+static inline int64_t pool_slots_bound(uint64_t n_walks)
+{
+    const uint64_t cap = (uint64_t)num_cu() * 32;
+    const uint64_t gmax = std::min<uint64_t>(cap, (n_walks + 63) / 64);
+    return (int64_t)std::min<uint64_t>(cap * (uint64_t)g_pool_n, n_walks + 64 * gmax + 64);
+}
+
 extern "C" int64_t wost_solve_workspace_bytes(const wost_geom* geom, int64_t n_points, int32_t wpp)
 {
     if (!geom || n_points < 0 || wpp <= 0) return -1;
-    return 256 + ((n_points * (int64_t)wpp * 4 + 255) & ~int64_t(255));
+    const uint64_t n_walks = (uint64_t)n_points * (uint64_t)wpp;
+    const int64_t slots = pool_slots_bound(n_walks);
+    return 256 + align256((int64_t)n_walks * 4) + align256(slots * pool_words(geom->dim) * 4) + align256(slots * 4 * 4);
+}
+
+extern "C" int wost_set_walk_pool(int32_t slots_per_wave, int32_t refill_batch)
+{
+    if (slots_per_wave == 0) slots_per_wave = 512;
+    if (refill_batch == 0) refill_batch = 16;
+    if (slots_per_wave < 64 || slots_per_wave > 8192 || slots_per_wave % 64) {
+        set_error("wost_set_walk_pool: slots_per_wave must be a multiple of 64 in [64, 8192] (0 = default)");
+        return WOST_EINVAL;
+    }
+    if (refill_batch < 1 || refill_batch > 64) {
+        set_error("wost_set_walk_pool: refill_batch must be in [1, 64] (0 = default)");
+        return WOST_EINVAL;
+    }
+    g_pool_n = slots_per_wave;
+    g_refill_batch = refill_batch;
+    return WOST_OK;
 }
 
 extern "C" int wost_set_cost_counters(uint64_t* dev_counters18)
@@ -634,8 +1025,26 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
         per_cu = nb;
     }
     const uint64_t waves_needed = (P.n_walks + 63) / 64;
-    const uint64_t cap = (uint64_t)num_cu() * (uint64_t)per_cu;
+    const uint64_t cap = (uint64_t)num_cu() * (uint64_t)std::min(per_cu, 32);
     const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(waves_needed, cap));
+    P.pool_n = pool_slots(P.n_walks, grid);
+    P.refill_batch = g_refill_batch;
+    P.pool_total = (int64_t)grid * P.pool_n;
+    {
+        // workspace: counter | per-walk values | pools | work lists
+        const int64_t vbytes = align256((int64_t)P.n_walks * 4);
+        const int64_t pbytes = align256(P.pool_total * pool_words(dim) * 4);
+        if ((uint64_t)P.pool_total * (uint64_t)pool_words(dim) >= (1ull << 32)) {
+            set_error("wost_solve: walk pools exceed 2^32 words; lower wost_set_walk_pool");
+            return WOST_EUNSUPPORTED;
+        }
+        if (P.pool_total > pool_slots_bound(P.n_walks) || 256 + vbytes + pbytes + align256(P.pool_total * 16) > ws_bytes) {
+            set_error("wost_solve: workspace too small for the launch");
+            return WOST_ESIZE;
+        }
+        P.pool = (uint32_t*)(ws + 256 + vbytes);
+        P.lists = (int32_t*)(ws + 256 + vbytes + pbytes);
+    }
     // about eight reservations per wave over the whole call, at least one lane's worth each
     P.chunk = std::max<uint64_t>(64, std::min<uint64_t>(4096, P.n_walks / ((uint64_t)grid * 8)));
     hipLaunchKernelGGL(fn, dim3(grid), dim3(64), lds, s, P);
