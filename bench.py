@@ -173,7 +173,7 @@ def main():
 
     # ---- roofline of the walk kernel: algorithmic bytes per step from an
     # instrumented pass over a sample of the same workload
-    cost = torch.zeros(12, dtype=torch.int64, device="cuda")
+    cost = torch.zeros(18, dtype=torch.int64, device="cuda")
     api.set_cost_counters(cost)
     sample = pts[:: max(1, s.n_points // 8192)]
     a_u = W.solve(geom, pb_u, sample, 16, seed=5)
