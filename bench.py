@@ -48,6 +48,37 @@ def bytes_per_step(cost, dim):
     return sum(c["nodes_per_step"] * nb + c["prims_per_step"] * kinds[q] for q, c in cost.items())
 
 
+WALK_SOURCES = ["walk.hip", "geom_device.h", "guide_device.h", "walk_common.h", "wost_internal.h", "../build.py"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_kernel2_c3_guided_traffic.md")
+
+
+def walk_sources_sha256():
+    """Hash of the sources and build flags of the walk kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2410_18944_amd", "csrc")
+    for f in WALK_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the guided walk kernel from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on
+    other kernel sources than the ones built here."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            for line in fh:
+                if line.startswith("traffic-json: "):
+                    rec = json.loads(line[len("traffic-json: "):])
+                    if rec.get("sources_sha256") == walk_sources_sha256():
+                        return rec
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(scene, max_seconds=20.0):
     import oracle
     oracle.build(force=False)
@@ -79,9 +110,13 @@ def main():
     ap.add_argument("--batch-wpp", type=int, default=16)
     ap.add_argument("--train-until", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--print-walk-sha", action="store_true", help="print the walk kernel source hash and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
+    if args.print_walk_sha:
+        print(walk_sources_sha256())
+        return
     if args.copy_probe_mib > 0:
         import torch
         n = args.copy_probe_mib * (1 << 20) // 4
@@ -187,12 +222,16 @@ def main():
     bps_g = bytes_per_step(cost_g, 2)
     # dominant kernel: the guided walk kernel; time = walk phase of the timed solves
     achieved = total_steps * bps_g / max(walk_s, 1e-9) / 1e9
+    tr = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(tr["hbm_bytes_per_launch"]) if tr else None,
                 "kernel": "wost::walk_kernel2<true, false> (guided 2D walk)",
                 "bytes_per_step": round(bps_g, 1), "uniform_bytes_per_step": round(bps_u, 1),
                 "walk_s": round(walk_s, 4), "steps": total_steps,
-                "launches": n_launch, "avg_launch_ms": round(walk_s / max(n_launch, 1) * 1e3, 3)}
+                "launches": n_launch, "avg_launch_ms": round(walk_s / max(n_launch, 1) * 1e3, 3),
+                "algorithmic_bytes_per_launch": round(total_steps * bps_g / max(n_launch, 1)),
+                "walk_sources_sha256": walk_sources_sha256()[:16]}
 
     cpu = None
     if not args.no_cpu:
