@@ -20,17 +20,40 @@ FLAGS = [
 ]
 
 
+# per-source extra flags: the walk kernel keeps machine-level loop-invariant
+# code motion off, which otherwise hoists per-phase values across all phases
+# of a walk round and costs resident waves (measured 4-6% faster)
+EXTRA = {"walk.hip": ["-mllvm", "-disable-machine-licm"]}
+
+
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), *srcs, "-o", tmp]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libwost.so")
-    if verbose:
-        sys.stderr.write(res.stderr)
-    os.replace(tmp, LIB)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    objs = []
+    tag = "%d" % os.getpid()
+    try:
+        for src in srcs:
+            obj = os.path.join(CSRC, src + ".o" + tag)
+            cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *EXTRA.get(src, []), *inc, "-c",
+                   os.path.join(CSRC, src), "-o", obj]
+            res = subprocess.run(cmd, capture_output=True, text=True)
+            if res.returncode != 0:
+                sys.stderr.write(res.stdout + res.stderr)
+                raise RuntimeError("hipcc failed compiling %s" % src)
+            if verbose:
+                sys.stderr.write(res.stderr)
+            objs.append(obj)
+        tmp = LIB + ".tmp" + tag
+        res = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
+                             capture_output=True, text=True)
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError("hipcc failed linking libwost.so")
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return LIB
 
 

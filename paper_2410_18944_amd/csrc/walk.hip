@@ -743,13 +743,25 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
     }
 }
 
-// 2D: at least four resident waves per SIMD (<= 128 VGPRs) keeps every
-// variant free of spills.  3D keeps the compiler's choice: its guide encoder
-// (16 levels x 8 corners) would spill under that bound.
-template <bool GUIDED, bool STATS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void walk_kernel2(const WalkParams P)
+// Register bounds per variant (resident waves per SIMD); the traversal
+// phases are latency-bound, so residency matters more than a few spills of
+// values that live across phases.
+#ifndef WOST_WAVES_2D_UNIFORM
+#define WOST_WAVES_2D_UNIFORM 5
+#endif
+#ifndef WOST_WAVES_2D_GUIDED
+#define WOST_WAVES_2D_GUIDED 4
+#endif
+template <bool STATS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WOST_WAVES_2D_UNIFORM))) void walk_kernel2u(const WalkParams P)
 {
-    walk_body<2, GUIDED, STATS>(P);
+    walk_body<2, false, STATS>(P);
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WOST_WAVES_2D_GUIDED))) void walk_kernel2g(const WalkParams P)
+{
+    walk_body<2, true, STATS>(P);
 }
 
 template <bool GUIDED, bool STATS>
@@ -874,6 +886,10 @@ static bool copy_field(const wost_field& in, int dim, FieldDev& out, const char*
 using namespace wost;
 
 static int g_pool_n = 512;   // walk slots per wave
+#ifndef WOST_POOL_MIN
+#define WOST_POOL_MIN 64
+#endif
+static int g_pool_min = WOST_POOL_MIN;   // fewest walks per wave before the grid shrinks
 
 static inline int64_t align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 static inline int pool_words(int dim) { return dim == 2 ? PoolField<2>::WORDS : PoolField<3>::WORDS; }
@@ -1011,8 +1027,8 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     using WalkFn = void (*)(const WalkParams);
     WalkFn fn;
     if (dim == 2) {
-        if (P.cost) fn = guided ? walk_kernel2<true, true> : walk_kernel2<false, true>;
-        else fn = guided ? walk_kernel2<true, false> : walk_kernel2<false, false>;
+        if (P.cost) fn = guided ? walk_kernel2g<true> : walk_kernel2u<true>;
+        else fn = guided ? walk_kernel2g<false> : walk_kernel2u<false>;
     } else {
         if (P.cost) fn = guided ? walk_kernel3<true, true> : walk_kernel3<false, true>;
         else fn = guided ? walk_kernel3<true, false> : walk_kernel3<false, false>;
@@ -1026,7 +1042,12 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     }
     const uint64_t waves_needed = (P.n_walks + 63) / 64;
     const uint64_t cap = (uint64_t)num_cu() * (uint64_t)std::min(per_cu, 32);
-    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(waves_needed, cap));
+    // fewer, fuller waves for launches that would leave pools short: each
+    // wave gets at least g_pool_min walks while the chip keeps at least
+    // 4 waves per CU
+    uint64_t want = waves_needed;
+    if (g_pool_min > 64) want = std::max<uint64_t>((uint64_t)num_cu() * 4, (P.n_walks + g_pool_min - 1) / g_pool_min);
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>(std::min<uint64_t>(waves_needed, want), cap));
     P.pool_n = pool_slots(P.n_walks, grid);
     P.refill_batch = g_refill_batch;
     P.pool_total = (int64_t)grid * P.pool_n;
