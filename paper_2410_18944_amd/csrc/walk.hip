@@ -764,10 +764,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WOST_WAVES_2
     walk_body<2, true, STATS>(P);
 }
 
-template <bool GUIDED, bool STATS>
-__global__ __launch_bounds__(64) void walk_kernel3(const WalkParams P)
+#ifndef WOST_WAVES_3D_UNIFORM
+#define WOST_WAVES_3D_UNIFORM 3
+#endif
+#ifndef WOST_WAVES_3D_GUIDED
+#define WOST_WAVES_3D_GUIDED 2
+#endif
+template <bool STATS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WOST_WAVES_3D_UNIFORM))) void walk_kernel3u(const WalkParams P)
 {
-    walk_body<3, GUIDED, STATS>(P);
+    walk_body<3, false, STATS>(P);
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WOST_WAVES_3D_GUIDED))) void walk_kernel3g(const WalkParams P)
+{
+    walk_body<3, true, STATS>(P);
 }
 
 __global__ void zero_u64(unsigned long long* p, int n)
@@ -1030,8 +1042,8 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
         if (P.cost) fn = guided ? walk_kernel2g<true> : walk_kernel2u<true>;
         else fn = guided ? walk_kernel2g<false> : walk_kernel2u<false>;
     } else {
-        if (P.cost) fn = guided ? walk_kernel3<true, true> : walk_kernel3<false, true>;
-        else fn = guided ? walk_kernel3<true, false> : walk_kernel3<false, false>;
+        if (P.cost) fn = guided ? walk_kernel3g<true> : walk_kernel3u<true>;
+        else fn = guided ? walk_kernel3g<false> : walk_kernel3u<false>;
     }
     const size_t lds = walk_lds_bytes(guided, geom->max_depth, guide_out_stride(P.guide));
     int per_cu = g_waves_per_cu;
