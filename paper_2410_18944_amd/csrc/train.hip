@@ -41,6 +41,8 @@ struct TrainArgs {
     float loss_scale;
     float* grad;            // gradient vector (grid part first)
     float* partials;        // [gridDim.x][p_mlp]
+    float* gco;             // coarse-level feature gradients [2 n_coarse][count]
+    int32_t n_coarse;       // levels below this are staged in gco, not scattered
     int32_t backward;
     int32_t p_mlp;
     int32_t off[kMaxLayers];   // layer weight offsets relative to the MLP start
@@ -412,6 +414,15 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
                         for (int lv = 0; lv < 2; ++lv) {
                             const int l = 8 * mb + 2 * g4 + lv;
                             const float gf0 = dz[cb][mb][2 * lv] * inv, gf1 = dz[cb][mb][2 * lv + 1] * inv;
+                            if (l < a.n_coarse) {
+                                // coarse levels: staged per record, scattered by coarse_scatter_kernel
+                                if (wvalid) {
+                                    const int64_t iw = tile * 64 + w;
+                                    a.gco[(int64_t)(2 * l) * a.count + iw] = gf0;
+                                    a.gco[(int64_t)(2 * l + 1) * a.count + iw] = gf1;
+                                }
+                                continue;
+                            }
                             if (!wvalid || (gf0 == 0.f && gf1 == 0.f)) continue;
                             const int N = g.res[l];
                             int cc[D];
@@ -470,6 +481,81 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
 }
 
 // grad[mlp] += sum over workgroup partials, fixed order (deterministic)
+// Feature gradients of the coarse dense levels: every record touches the same
+// few thousand cells, so scattering them with global atomics serialises on a
+// handful of addresses.  Each workgroup accumulates its share of the records
+// into a private LDS copy of those levels (LDS fp32 atomics) and then adds
+// the non-zero entries to the gradient once.
+template <int D>
+__global__ __launch_bounds__(512) void coarse_scatter_kernel(const GuideDev g, const float* rec, int64_t cap,
+                                                             int64_t begin, int64_t count, const float* gco,
+                                                             int n_coarse, float* grad)
+{
+    extern __shared__ float s_g[];
+    int total = 0;
+    for (int l = 0; l < n_coarse; ++l) {
+        int cells = 1;
+        for (int d = 0; d < D; ++d) cells *= g.res[l] + 1;
+        total += 2 * cells;
+    }
+    for (int j = threadIdx.x; j < total; j += blockDim.x) s_g[j] = 0.f;
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        float x[D], xh[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) x[d] = rec[(int64_t)d * cap + begin + i];
+        normalise_input<D>(g, x, xh);
+        int lo = 0;
+        for (int l = 0; l < n_coarse; ++l) {
+            const int N = g.res[l];
+            const float gf0 = gco[(int64_t)(2 * l) * count + i], gf1 = gco[(int64_t)(2 * l + 1) * count + i];
+            int cells = 1;
+            for (int d = 0; d < D; ++d) cells *= N + 1;
+            if (gf0 != 0.f || gf1 != 0.f) {
+                int cc[D];
+                float fr[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const float pos = xh[d] * (float)N;
+                    int ci = (int)floorf(pos);
+                    ci = min(max(ci, 0), N - 1);
+                    cc[d] = ci;
+                    fr[d] = pos - (float)ci;
+                }
+#pragma unroll
+                for (int corner = 0; corner < (1 << D); ++corner) {
+                    float wt = 1.f;
+                    int idx = 0, st = 1;
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        const int b = (corner >> d) & 1;
+                        wt *= b ? fr[d] : 1.f - fr[d];
+                        idx += (cc[d] + b) * st;
+                        st *= N + 1;
+                    }
+                    atomicAdd(&s_g[lo + 2 * idx], wt * gf0);
+                    atomicAdd(&s_g[lo + 2 * idx + 1], wt * gf1);
+                }
+            }
+            lo += 2 * cells;
+        }
+    }
+    __syncthreads();
+    const int64_t T = 1ll << g.log2T;
+    int lo = 0;
+    for (int l = 0; l < n_coarse; ++l) {
+        int cells = 1;
+        for (int d = 0; d < D; ++d) cells *= g.res[l] + 1;
+        float* gl = grad + (int64_t)l * T * 2;
+        for (int j = threadIdx.x; j < 2 * cells; j += blockDim.x) {
+            const float v = s_g[lo + j];
+            if (v != 0.f) atomicAdd(gl + j, v);
+        }
+        lo += 2 * cells;
+    }
+}
+
 __global__ void reduce_partials(const float* partials, int nblk, int p_mlp, float* grad_mlp)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -529,6 +615,51 @@ static int train_grid_cap()
     return 2 * g_train_cu;
 }
 
+// LDS budget of the coarse-level scatter: the longest prefix of dense levels
+// whose two features fit in it is staged and scattered through LDS.
+constexpr int64_t kCoarseLdsFloats = 24 * 1024;
+
+static int coarse_levels(const GuideDev& g)
+{
+    int64_t total = 0;
+    int n = 0;
+    for (int l = 0; l < g.L; ++l) {
+        if (!g.dense[l]) break;
+        int64_t cells = 1;
+        for (int d = 0; d < g.dim; ++d) cells *= g.res[l] + 1;
+        if (total + 2 * cells > kCoarseLdsFloats) break;
+        total += 2 * cells;
+        ++n;
+    }
+    return n;
+}
+
+static int64_t coarse_lds_floats(const GuideDev& g, int n_coarse)
+{
+    int64_t total = 0;
+    for (int l = 0; l < n_coarse; ++l) {
+        int64_t cells = 1;
+        for (int d = 0; d < g.dim; ++d) cells *= g.res[l] + 1;
+        total += 2 * cells;
+    }
+    return total;
+}
+
+static int coarse_scatter_grid(int64_t count)
+{
+    // about 2048 records per workgroup, at most half a workgroup per CU: the
+    // flush adds (grid x staged entries) global atomics
+    const int64_t want = (count + 2047) / 2048;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::max(1, train_grid_cap() / 4)));
+}
+
+static int64_t train_ws_partials(const wost_guide* gd, int64_t count)
+{
+    const int64_t n_tiles = (count + 63) / 64;
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_tiles, train_grid_cap()));
+    return (grid * (gd->n_params - gd->n_grid) * 4 + 255) / 256 * 256;
+}
+
 static size_t train_lds_bytes(const wost_guide* gd, bool backward)
 {
     const GuideDev& g = gd->dev;
@@ -576,17 +707,31 @@ static int launch_train(const wost_guide* gd, const wost_records* rec, int64_t b
     const int grid = (int)std::min<int64_t>(n_tiles, train_grid_cap());
     if (backward) {
         if (!grad) { set_error("guide training: no gradient buffer bound"); return WOST_ESTATE; }
-        const int64_t need = (int64_t)grid * a.p_mlp * 4;
+        a.n_coarse = coarse_levels(g);
+        const int64_t part = train_ws_partials(gd, count);
+        const int64_t need = part + (int64_t)2 * a.n_coarse * count * 4;
         if (!workspace || ws_bytes < need) { set_error("guide training: workspace %lld < %lld", (long long)ws_bytes, (long long)need); return WOST_ESIZE; }
         a.partials = (float*)workspace;
+        a.gco = a.n_coarse ? (float*)((char*)workspace + part) : nullptr;
     }
     const size_t lds = train_lds_bytes(gd, backward);
     if (lds > 160 * 1024) { set_error("guide training: configuration needs %zu bytes of LDS", lds); return WOST_EUNSUPPORTED; }
     if (g.dim == 2) hipLaunchKernelGGL(train_kernel<2>, dim3(grid), dim3(64), lds, s, g, a);
     else hipLaunchKernelGGL(train_kernel<3>, dim3(grid), dim3(64), lds, s, g, a);
-    if (backward)
+    if (backward) {
         hipLaunchKernelGGL(reduce_partials, dim3((a.p_mlp + 255) / 256), dim3(256), 0, s, (const float*)a.partials, grid,
                            a.p_mlp, grad + gd->n_grid);
+        if (a.n_coarse) {
+            const size_t cl = sizeof(float) * (size_t)coarse_lds_floats(g, a.n_coarse);
+            const int cg = coarse_scatter_grid(count);
+            if (g.dim == 2)
+                hipLaunchKernelGGL(coarse_scatter_kernel<2>, dim3(cg), dim3(512), cl, s, g, (const float*)a.rec, a.cap,
+                                   a.begin, a.count, (const float*)a.gco, a.n_coarse, grad);
+            else
+                hipLaunchKernelGGL(coarse_scatter_kernel<3>, dim3(cg), dim3(512), cl, s, g, (const float*)a.rec, a.cap,
+                                   a.begin, a.count, (const float*)a.gco, a.n_coarse, grad);
+        }
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("guide training: launch failed: %s", hipGetErrorString(e)); return WOST_EHIP; }
     return WOST_OK;
@@ -599,9 +744,7 @@ using namespace wost;
 extern "C" int64_t wost_guide_train_workspace_bytes(const wost_guide* g, int64_t count)
 {
     if (!g || count < 0) return -1;
-    const int64_t n_tiles = (count + 63) / 64;
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_tiles, train_grid_cap()));
-    return grid * (g->n_params - g->n_grid) * 4 + 256;
+    return train_ws_partials(g, count) + (int64_t)2 * coarse_levels(g->dev) * count * 4 + 256;
 }
 
 extern "C" int wost_tail_pass(int32_t dim, const wost_records* rec, const float* walk_value, int64_t n_slots,

@@ -333,6 +333,13 @@ def test_loss_and_backward_match_fp64_reference(W, dim):
     rel_grid = np.linalg.norm(grad[:ng] - ref_grad[:ng]) / np.linalg.norm(ref_grad[:ng])
     say("grad rel err: all %.2e mlp %.2e grid %.2e" % (rel, rel_mlp, rel_grid))
     assert rel < 1e-3 and rel_mlp < 1e-3 and rel_grid < 1e-3
+    # level by level: the coarse dense levels are accumulated through LDS, the
+    # finer ones by direct atomics, and each must hold on its own
+    per = rcfg.T * rcfg.F
+    lvl = [np.linalg.norm(grad[l * per:(l + 1) * per] - ref_grad[l * per:(l + 1) * per])
+           / np.linalg.norm(ref_grad[l * per:(l + 1) * per]) for l in range(rcfg.L)]
+    say("grid rel err per level: " + " ".join("%.1e" % e for e in lvl))
+    assert max(lvl) < 5e-3
 
 
 def test_train_step_fits_known_target(W):
