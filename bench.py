@@ -29,7 +29,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES = {2: 80, 3: 96}
+# bytes read per four-wide node visit: child boxes and references, plus the
+# subtree measures (Neumann sample) or normal cones (silhouettes)
+NODE_BYTES = {d: {"closest_dirichlet": 16 * (2 * d + 1), "silhouette": 16 * (3 * d + 2),
+                  "neumann_sample": 16 * (2 * d + 2), "neumann_visibility": 16 * (2 * d + 1),
+                  "source_visibility": 16 * (2 * d + 1), "first_hit": 16 * (2 * d + 1)} for d in (2, 3)}
 PRIM_BYTES = {2: {"dir": 16, "sil": 32, "neu": 32}, 3: {"dir": 48, "sil": 64, "neu": 64}}
 
 
@@ -45,7 +49,7 @@ def bytes_per_step(cost, dim):
     pb = PRIM_BYTES[dim]
     kinds = {"closest_dirichlet": pb["dir"], "silhouette": pb["sil"], "neumann_sample": pb["neu"],
              "neumann_visibility": pb["neu"], "source_visibility": pb["neu"], "first_hit": pb["neu"]}
-    return sum(c["nodes_per_step"] * nb + c["prims_per_step"] * kinds[q] for q, c in cost.items())
+    return sum(c["nodes_per_step"] * nb[q] + c["prims_per_step"] * kinds[q] for q, c in cost.items())
 
 
 WALK_SOURCES = ["walk.hip", "geom_device.h", "guide_device.h", "walk_common.h", "wost_internal.h", "../build.py"]

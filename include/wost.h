@@ -93,7 +93,8 @@ typedef struct {
  * give WOST_EINVAL.  On success *out owns a host image of the device layout. */
 typedef struct {
     int32_t leaf_size;      /* max primitives per leaf (default 4, 1..64)             */
-    int32_t brute_force;    /* 1: a single leaf per hierarchy (exhaustive queries)     */
+    int32_t brute_force;    /* 1: exhaustive queries: leaves of 64 primitives whose
+                               boxes cover the whole hierarchy, no cone culling      */
 } wost_build_opts;
 
 int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, const int32_t* prims,
@@ -105,7 +106,9 @@ int64_t wost_geom_device_bytes(const wost_geom* geom);
  * call that uses `geom`.  Re-uploading to another buffer is allowed. */
 int wost_geom_upload(wost_geom* geom, void* dev_buf, int64_t bytes, void* stream);
 /* Scene statistics: out[0..7] = dim, n_dirichlet, n_neumann, n_silhouette,
- * max BVH depth, AABB diagonal, bytes, 0. */
+ * deepest binary split level, AABB diagonal, bytes, traversal stack entries
+ * per lane (the hierarchies are stored four-wide: every node holds the
+ * children of a binary node with inner children replaced by their own). */
 int wost_geom_info(const wost_geom* geom, double* out8);
 /* Map a library-internal primitive id (as returned by wost_query) to the
  * caller's primitive index; returns -1 if out of range. */

@@ -86,7 +86,7 @@ struct Builder {
     void build(int b, int e, int depth, int32_t& out_c, int32_t& out_n)
     {
         max_depth = std::max(max_depth, depth);
-        if (e - b <= leaf || brute) {
+        if (e - b <= leaf) {
             out_c = (int32_t)order.size();
             out_n = e - b;
             for (int i = b; i < e; ++i) order.push_back((*items)[i].id);
@@ -122,7 +122,7 @@ struct Builder {
         int n = (int)items->size();
         if (n == 0) return;
         int32_t c, k;
-        if (n <= leaf || brute) {
+        if (n <= leaf) {
             nodes.emplace_back();
             build(0, n, 1, c, k);
             nodes[0].box[0] = range_box(0, n);
@@ -186,7 +186,7 @@ wost::DevGeom wost_geom::devgeom() const
     const uint8_t* base = (const uint8_t*)dev;
     DevBvh* b[3] = {&g.dir, &g.neu, &g.sil};
     for (int i = 0; i < 3; ++i) {
-        b[i]->nodes = base + sec[i].nodes;
+        b[i]->nodes = (const float4*)(base + sec[i].nodes);
         b[i]->prims = (const float4*)(base + sec[i].prims);
         b[i]->pextra = sec[i].pextra >= 0 ? (const float4*)(base + sec[i].pextra) : nullptr;
         b[i]->orig = sec[i].orig >= 0 ? (const int32_t*)(base + sec[i].orig) : nullptr;
@@ -336,14 +336,12 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
                 items.push_back(it);
             }
         }
-        Builder B{d, leaf, brute, &items, {}, {}, 0};
+        // brute force: leaves of the maximum size whose boxes all cover the
+        // whole hierarchy and cones that never cull, so every query tests
+        // every primitive
+        Builder B{d, brute ? kLeafMax : leaf, brute, &items, {}, {}, 0};
         B.run();
         g->max_depth = std::max(g->max_depth, B.max_depth);
-        if (B.max_depth > kMaxDepth) {
-            set_error("wost_build_bvh: hierarchy depth %d exceeds %d", B.max_depth, kMaxDepth);
-            delete g;
-            return WOST_EUNSUPPORTED;
-        }
         const int nn = (int)B.nodes.size();
         const int np = (int)B.order.size();
         // structural validation: every child reference in range, every item in
@@ -428,7 +426,7 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
         auto fbox = [](const Box& b, int i, bool hi) {
             return hi ? std::nextafter((float)b.hi[i], INFINITY) : std::nextafter((float)b.lo[i], -INFINITY);
         };
-        auto aux = [&](int ni, int ch) {
+        auto aux_of = [&](int ni, int ch) {
             if (which == 1) return make_float4((float)sub_meas[ni * 2 + ch], 0.f, 0.f, 0.f);
             if (which == 2) {
                 // normal cone as (axis, cos of the half-angle); cos <= 0 marks
@@ -437,39 +435,120 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
                 // the stored cone contains the exact one.
                 auto& c = sub_cone[ni * 2 + ch];
                 const double ch_ = std::cos(c[3]);
-                const float cw = c[3] >= 0.5 * M_PI ? -1.f : std::nextafter((float)ch_, -INFINITY);
+                const float cw = (c[3] >= 0.5 * M_PI || brute) ? -1.f : std::nextafter((float)ch_, -INFINITY);
                 return make_float4((float)c[0], (float)c[1], (float)c[2], cw);
             }
             return make_float4(0.f, 0.f, 0.f, 0.f);
         };
-        int64_t off_nodes;
-        if (d == 2) {
-            std::vector<Node2> out(nn);
-            for (int ni = 0; ni < nn; ++ni) {
-                const BuiltNode& nd = B.nodes[ni];
-                Node2& o = out[ni];
-                o.b0 = make_float4(fbox(nd.box[0], 0, 0), fbox(nd.box[0], 1, 0), fbox(nd.box[0], 0, 1), fbox(nd.box[0], 1, 1));
-                o.b1 = make_float4(fbox(nd.box[1], 0, 0), fbox(nd.box[1], 1, 0), fbox(nd.box[1], 0, 1), fbox(nd.box[1], 1, 1));
-                o.ch = make_int4(nd.c[0], nd.n[0], nd.c[1], nd.n[1]);
-                o.aux0 = aux(ni, 0);
-                o.aux1 = aux(ni, 1);
+        // ---- collapse into four-wide nodes: a node holds the children of a
+        // binary node, with every inner child replaced by its own two
+        // children (breadth first, so every inner reference points forward)
+        struct Ent { int bn, ch; };                 // child `ch` of binary node `bn`
+        std::vector<std::array<Ent, 4>> ent4;
+        std::vector<int> n_ent4, depth4;
+        std::vector<int> of_binary(nn, -1);         // binary node -> four-wide node
+        int max_d4 = 0;
+        if (nn > 0) {
+            std::vector<int> queue{0};
+            of_binary[0] = 0;
+            ent4.emplace_back();
+            n_ent4.push_back(0);
+            depth4.push_back(1);
+            for (size_t qi = 0; qi < queue.size(); ++qi) {
+                const int bn = queue[qi];
+                const int me = of_binary[bn];
+                max_d4 = std::max(max_d4, depth4[me]);
+                std::array<Ent, 4> e{};
+                int m = 0;
+                const BuiltNode& nd = B.nodes[bn];
+                for (int ch = 0; ch < 2; ++ch) {
+                    if (nd.n[ch] > 0) { e[m++] = {bn, ch}; continue; }
+                    if (nd.c[ch] < 0) continue;
+                    const BuiltNode& cd = B.nodes[nd.c[ch]];
+                    for (int gch = 0; gch < 2; ++gch)
+                        if (cd.n[gch] > 0 || cd.c[gch] >= 0) e[m++] = {nd.c[ch], gch};
+                }
+                for (int k = 0; k < m; ++k) {
+                    const BuiltNode& pn = B.nodes[e[k].bn];
+                    if (pn.n[e[k].ch] > 0) continue;
+                    const int child = pn.c[e[k].ch];
+                    of_binary[child] = (int)ent4.size();
+                    ent4.emplace_back();
+                    n_ent4.push_back(0);
+                    depth4.push_back(depth4[me] + 1);
+                    queue.push_back(child);
+                }
+                ent4[me] = e;
+                n_ent4[me] = m;
             }
-            off_nodes = push_bytes(img, out.data(), out.size());
-        } else {
-            std::vector<Node3> out(nn);
-            for (int ni = 0; ni < nn; ++ni) {
-                const BuiltNode& nd = B.nodes[ni];
-                Node3& o = out[ni];
-                const Box &x0 = nd.box[0], &x1 = nd.box[1];
-                o.b0a = make_float4(fbox(x0, 0, 0), fbox(x0, 1, 0), fbox(x0, 2, 0), fbox(x0, 0, 1));
-                o.b0b = make_float4(fbox(x0, 1, 1), fbox(x0, 2, 1), fbox(x1, 0, 0), fbox(x1, 1, 0));
-                o.b1b = make_float4(fbox(x1, 2, 0), fbox(x1, 0, 1), fbox(x1, 1, 1), fbox(x1, 2, 1));
-                o.ch = make_int4(nd.c[0], nd.n[0], nd.c[1], nd.n[1]);
-                o.aux0 = aux(ni, 0);
-                o.aux1 = aux(ni, 1);
-            }
-            off_nodes = push_bytes(img, out.data(), out.size());
         }
+        const int n4 = (int)ent4.size();
+        // a lane defers at most three children per level of its path
+        const int stack_need = 3 * std::max(max_d4 - 1, 0) + 1;
+        g->stack_entries = std::max(g->stack_entries, stack_need);
+        if (stack_need > kMaxStack || (int64_t)np > kMaxLeafFirst || leaf > kLeafMax) {
+            set_error("wost_build_bvh: hierarchy %d too deep or too large (stack %d > %d or %d primitives)", which,
+                      stack_need, kMaxStack, np);
+            delete g;
+            return WOST_EUNSUPPORTED;
+        }
+        const int stride = which == 0 ? 2 * d + 1 : which == 1 ? 2 * d + 2 : 3 * d + 2;
+        const Box all_box = B.range_box(0, (int)items.size());
+        std::vector<float4> nodes4((size_t)n4 * stride);
+        for (int i = 0; i < n4; ++i) {
+            float lo[3][4], hi[3][4], aux[4][4];
+            int32_t ref[4];
+            for (int k = 0; k < 4; ++k) {
+                for (int a = 0; a < 3; ++a) { lo[a][k] = INFINITY; hi[a][k] = -INFINITY; }
+                for (int a = 0; a < 4; ++a) aux[a][k] = 0.f;
+                ref[k] = kEmptyRef;
+                if (k >= n_ent4[i]) continue;
+                const Ent en = ent4[i][k];
+                const BuiltNode& pn = B.nodes[en.bn];
+                const Box& cb = brute ? all_box : pn.box[en.ch];
+                for (int a = 0; a < d; ++a) { lo[a][k] = fbox(cb, a, 0); hi[a][k] = fbox(cb, a, 1); }
+                ref[k] = pn.n[en.ch] > 0 ? leaf_ref(pn.c[en.ch], pn.n[en.ch]) : of_binary[pn.c[en.ch]];
+                const float4 ax = aux_of(en.bn, en.ch);
+                if (which == 1) aux[0][k] = ax.x;
+                if (which == 2) {
+                    const float v[4] = {ax.x, ax.y, ax.z, ax.w};
+                    for (int a = 0; a < d; ++a) aux[a][k] = v[a];
+                    aux[d][k] = v[3];
+                }
+            }
+            float4* o = &nodes4[(size_t)i * stride];
+            for (int a = 0; a < d; ++a) {
+                o[a] = make_float4(lo[a][0], lo[a][1], lo[a][2], lo[a][3]);
+                o[d + a] = make_float4(hi[a][0], hi[a][1], hi[a][2], hi[a][3]);
+            }
+            int4 r = make_int4(ref[0], ref[1], ref[2], ref[3]);
+            memcpy(&o[2 * d], &r, sizeof(r));
+            const int n_aux = which == 1 ? 1 : which == 2 ? d + 1 : 0;
+            for (int a = 0; a < n_aux; ++a) o[2 * d + 1 + a] = make_float4(aux[a][0], aux[a][1], aux[a][2], aux[a][3]);
+        }
+        // validation of the four-wide references (the kernels index without checks)
+        {
+            std::vector<int> seen(np, 0);
+            bool ok = (n4 > 0) == (np > 0);
+            for (int i = 0; i < n4 && ok; ++i) {
+                int32_t r[4];
+                memcpy(r, &nodes4[(size_t)i * stride + 2 * d], sizeof(r));
+                for (int k = 0; k < 4 && ok; ++k) {
+                    if (r[k] == kEmptyRef) continue;
+                    if (r[k] >= 0) { ok = r[k] > i && r[k] < n4; continue; }
+                    const int f = leaf_first(r[k]), c = leaf_count(r[k]);
+                    ok = f >= 0 && c >= 1 && f + c <= np;
+                    for (int j = f; ok && j < f + c; ++j) seen[j]++;
+                }
+            }
+            for (int j = 0; j < np && ok; ++j) ok = seen[j] == 1;
+            if (!ok) {
+                set_error("wost_build_bvh: internal error: four-wide hierarchy %d failed validation", which);
+                delete g;
+                return WOST_EINVAL;
+            }
+        }
+        const int64_t off_nodes = push_bytes(img, nodes4.data(), nodes4.size());
         std::vector<float4> pr;
         std::vector<float4> px;
         std::vector<int32_t> orig;
@@ -510,7 +589,7 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
         int64_t off_prims = push_bytes(img, pr.data(), pr.size());
         int64_t off_px = which == 1 ? push_bytes(img, px.data(), px.size()) : -1;
         int64_t off_orig = which < 2 ? push_bytes(img, orig.data(), orig.size()) : -1;
-        g->sec[which] = {off_nodes, off_prims, off_px, off_orig, nn, np};
+        g->sec[which] = {off_nodes, off_prims, off_px, off_orig, n4, np};
         if (which == 0) g->n_dir = np;
         if (which == 1) {
             g->n_neu = np;
@@ -548,7 +627,7 @@ extern "C" int wost_geom_info(const wost_geom* g, double* o)
 {
     if (!g || !o) { set_error("wost_geom_info: NULL argument"); return WOST_EINVAL; }
     o[0] = g->dim; o[1] = (double)g->n_dir; o[2] = (double)g->n_neu; o[3] = (double)g->n_sil;
-    o[4] = g->max_depth; o[5] = g->diag; o[6] = (double)g->bytes; o[7] = 0;
+    o[4] = g->max_depth; o[5] = g->diag; o[6] = (double)g->bytes; o[7] = g->stack_entries;
     return WOST_OK;
 }
 

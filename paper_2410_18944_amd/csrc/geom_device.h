@@ -43,33 +43,42 @@ __device__ __forceinline__ void stat_prim(NoStat*) {}
 __device__ __forceinline__ void stat_node(Stat* s) { ++s->nodes; }
 __device__ __forceinline__ void stat_prim(Stat* s) { ++s->prims; }
 
-__device__ __forceinline__ void load_node(const Node2* nodes, int i, Box<2>& b0, Box<2>& b1, int4& ch,
-                                          float4& a0, float4& a1)
+// component k of a float4 / int4 (k is a compile-time constant after unrolling)
+__device__ __forceinline__ float comp(const float4& v, int k)
 {
-    const Node2 n = nodes[i];
-    b0.lo[0] = n.b0.x; b0.lo[1] = n.b0.y; b0.hi[0] = n.b0.z; b0.hi[1] = n.b0.w;
-    b1.lo[0] = n.b1.x; b1.lo[1] = n.b1.y; b1.hi[0] = n.b1.z; b1.hi[1] = n.b1.w;
-    ch = n.ch; a0 = n.aux0; a1 = n.aux1;
+    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+}
+__device__ __forceinline__ int comp(const int4& v, int k)
+{
+    return k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
 }
 
-__device__ __forceinline__ void load_node(const Node3* nodes, int i, Box<3>& b0, Box<3>& b1, int4& ch,
-                                          float4& a0, float4& a1)
-{
-    const Node3 n = nodes[i];
-    b0.lo[0] = n.b0a.x; b0.lo[1] = n.b0a.y; b0.lo[2] = n.b0a.z;
-    b0.hi[0] = n.b0a.w; b0.hi[1] = n.b0b.x; b0.hi[2] = n.b0b.y;
-    b1.lo[0] = n.b0b.z; b1.lo[1] = n.b0b.w; b1.lo[2] = n.b1b.x;
-    b1.hi[0] = n.b1b.y; b1.hi[1] = n.b1b.z; b1.hi[2] = n.b1b.w;
-    ch = n.ch; a0 = n.aux0; a1 = n.aux1;
-}
+// The four children's boxes and references of one four-wide node.
+template <int D> struct Node4 {
+    float4 lo[D], hi[D];
+    int4 ref;
+    __device__ __forceinline__ Box<D> box(int k) const
+    {
+        Box<D> b;
+#pragma unroll
+        for (int a = 0; a < D; ++a) { b.lo[a] = comp(lo[a], k); b.hi[a] = comp(hi[a], k); }
+        return b;
+    }
+};
 
-// lightweight variant: boxes and children only (aux skipped)
 template <int D>
-__device__ __forceinline__ void load_node_boxes(const typename NodeT<D>::type* nodes, int i, Box<D>& b0,
-                                                Box<D>& b1, int4& ch)
+__device__ __forceinline__ const float4* node_ptr(const float4* nodes, int i, int stride)
 {
-    float4 a0, a1;
-    load_node(nodes, i, b0, b1, ch, a0, a1);
+    return nodes + (size_t)i * (size_t)stride;
+}
+
+template <int D>
+__device__ __forceinline__ void load_node4(const float4* p, Node4<D>& n)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) { n.lo[a] = p[a]; n.hi[a] = p[D + a]; }
+    const float4 r = p[2 * D];
+    n.ref = make_int4(__float_as_int(r.x), __float_as_int(r.y), __float_as_int(r.z), __float_as_int(r.w));
 }
 
 template <int D>
@@ -303,20 +312,38 @@ struct Trav {
     int prim;
 };
 
-// After the children of a node were tested: descend into the nearer live
-// child and defer the other, or resume from the deepest deferred entry whose
-// key is still below `best`.  Returns false when nothing is left.
-__device__ __forceinline__ bool trav_next(bool v0, bool v1, float k0, float k1, const int4& ch, float best,
-                                          Trav& q, const LdsStack& st)
+// After the children of a node were tested: descend into the live inner
+// child with the smallest key and defer the others (farthest pushed first, so
+// they come back nearest first), or resume from the deepest deferred entry
+// whose key is still below `best`.  key[k] = +inf marks a child that is not
+// followed.  Returns false when nothing is left.
+__device__ __forceinline__ void sort_ce(float& ka, int& ra, float& kb, int& rb)
 {
-    if (v0 && v1) {
-        const bool first0 = k0 <= k1;
-        st.put(q.sp++, first0 ? ch.z : ch.x, first0 ? k1 : k0);
-        q.node = first0 ? ch.x : ch.z;
+    const bool sw = kb < ka;
+    const float tk = sw ? kb : ka;
+    const int tr = sw ? rb : ra;
+    kb = sw ? ka : kb;
+    rb = sw ? ra : rb;
+    ka = tk;
+    ra = tr;
+}
+
+__device__ __forceinline__ bool trav_next4(float k0, float k1, float k2, float k3, const int4& ref, float best,
+                                           Trav& q, const LdsStack& st)
+{
+    int r0 = ref.x, r1 = ref.y, r2 = ref.z, r3 = ref.w;
+    sort_ce(k0, r0, k1, r1);
+    sort_ce(k2, r2, k3, r3);
+    sort_ce(k0, r0, k2, r2);
+    sort_ce(k1, r1, k3, r3);
+    sort_ce(k1, r1, k2, r2);
+    if (k0 < INFINITY) {
+        if (k3 < INFINITY) st.put(q.sp++, r3, k3);
+        if (k2 < INFINITY) st.put(q.sp++, r2, k2);
+        if (k1 < INFINITY) st.put(q.sp++, r1, k1);
+        q.node = r0;
         return true;
     }
-    if (v0) { q.node = ch.x; return true; }
-    if (v1) { q.node = ch.z; return true; }
     while (q.sp > 0) {
         const uint2 e = st.get(--q.sp);
         if (__uint_as_float(e.y) < best) { q.node = (int)e.x; return true; }
@@ -333,48 +360,56 @@ __device__ __forceinline__ void trav_begin(const DevBvh& b, float best, Trav& q)
     q.prim = -1;
 }
 
+// leaf children of a node whose key passes, as a bit mask
+template <class F>
+__device__ __forceinline__ uint32_t leaf_mask(const int4& ref, F pass)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int r = comp(ref, k);
+        if (r < 0 && r != kEmptyRef && pass(k)) m |= 1u << k;
+    }
+    return m;
+}
+
 // ---- closest Dirichlet point: q.best = squared distance, q.prim = primitive
 template <int D, class S>
 __device__ __forceinline__ bool closest_dirichlet_step(const DevBvh& b, const float* x, Trav& q, const LdsStack& st,
                                                        S* s)
 {
     if (q.node < 0) return true;
-    using NodeType = typename NodeT<D>::type;
-    Box<D> b0, b1;
-    int4 ch;
-    load_node_boxes<D>((const NodeType*)b.nodes, q.node, b0, b1, ch);
+    Node4<D> n;
+    load_node4<D>(node_ptr<D>(b.nodes, q.node, Layout4<D>::kDirStride), n);
     stat_node(s);
-    const float d0 = box_dist2<D>(b0, x), d1 = box_dist2<D>(b1, x);
-    bool v0 = d0 < q.best, v1 = d1 < q.best;
-    if (v0 && ch.y > 0) {
-        for (int k = ch.x; k < ch.x + ch.y; ++k) {
-            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-            float c[D];
-            const float dd = pr.closest(x, c);
-            if (dd < q.best) { q.best = dd; q.prim = k; }
+    float key[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) key[k] = box_dist2<D>(n.box(k), x);   // empty children: +inf
+    uint32_t lm = leaf_mask(n.ref, [&](int k) { return key[k] < q.best; });
+    while (lm) {
+        const int k = __builtin_ctz(lm);
+        lm &= lm - 1;
+        const int r = comp(n.ref, k);
+        const int f = leaf_first(r), c = leaf_count(r);
+        for (int j = f; j < f + c; ++j) {
+            Prim<D> pr; pr.load(b.prims, j); stat_prim(s);
+            float cp[D];
+            const float dd = pr.closest(x, cp);
+            if (dd < q.best) { q.best = dd; q.prim = j; }
         }
-        v0 = false;
     }
-    if (v1 && ch.w > 0) {
-        for (int k = ch.z; k < ch.z + ch.w; ++k) {
-            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-            float c[D];
-            const float dd = pr.closest(x, c);
-            if (dd < q.best) { q.best = dd; q.prim = k; }
-        }
-        v1 = false;
-    }
-    v0 = v0 && d0 < q.best;
-    v1 = v1 && d1 < q.best;
-    return !trav_next(v0, v1, d0, d1, ch, q.best, q, st);
+    float kk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) kk[k] = comp(n.ref, k) >= 0 && key[k] < q.best ? key[k] : INFINITY;
+    return !trav_next4(kk[0], kk[1], kk[2], kk[3], n.ref, q.best, q, st);
 }
 
 // ----------------------------------------------------------------- silhouettes
 
-// true if the normal cone (axis, half-angle) of a child cannot contain a
-// silhouette as seen from x: every primitive normal inside the cone makes an
-// angle below pi/2 (all front) or above pi/2 (all back) with x - p for every
-// p in the box.
+// true if the normal cone (axis, cos of the half-angle) of a child cannot
+// contain a silhouette as seen from x: every primitive normal inside the cone
+// makes an angle below pi/2 (all front) or above pi/2 (all back) with x - p
+// for every p in the box.
 template <int D>
 __device__ __forceinline__ bool cone_culls(const Box<D>& b, const float4& cone, const float* x)
 {
@@ -387,6 +422,26 @@ __device__ __forceinline__ bool cone_culls(const Box<D>& b, const float4& cone, 
     // plus a margin of 1e-3 |v| (about 1e-3 rad of beta) for rounding.
     const float ct = cone.w;
     if (!(ct > 0.f)) return false;
+    if constexpr (D == 2) {
+        // In 2D the four corners are cheap and bound the box exactly: x - p
+        // over the box is the convex hull of x - corner, and the directions
+        // making an angle below pi/2 - theta with the axis (or above
+        // pi/2 + theta) form a convex cone, so testing the corners decides
+        // the whole box.  |d.axis| > (sin theta + 1e-3) |d| in squares.
+        const float sm = sqrtf(fmaxf(1.f - ct * ct, 0.f)) + 1e-3f;
+        const float sm2 = sm * sm;
+        bool front = true, back = true;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float d0 = x[0] - ((c & 1) ? b.hi[0] : b.lo[0]);
+            const float d1 = x[1] - ((c & 2) ? b.hi[1] : b.lo[1]);
+            const float da = fmaf(d1, cone.y, d0 * cone.x);
+            const bool out = da * da > sm2 * fmaf(d1, d1, d0 * d0);
+            front = front && out && da > 0.f;
+            back = back && out && da < 0.f;
+        }
+        return front || back;
+    }
     float v[D], R2 = 0.f, dist2 = 0.f, va = 0.f;
     const float ax[3] = {cone.x, cone.y, cone.z};
 #pragma unroll
@@ -446,26 +501,34 @@ __device__ __forceinline__ bool closest_silhouette_step(const DevBvh& b, const f
                                                         const LdsStack& st, S* s)
 {
     if (q.node < 0) return true;
-    using NodeType = typename NodeT<D>::type;
-    Box<D> b0, b1;
-    int4 ch;
-    float4 c0, c1;
-    load_node((const NodeType*)b.nodes, q.node, b0, b1, ch, c0, c1);
+    const float4* p = node_ptr<D>(b.nodes, q.node, Layout4<D>::kSilStride);
+    Node4<D> n;
+    load_node4<D>(p, n);
+    float4 cn[D + 1];
+#pragma unroll
+    for (int a = 0; a <= D; ++a) cn[a] = p[Layout4<D>::kAux + a];
     stat_node(s);
-    const float d0 = box_dist2<D>(b0, x), d1 = box_dist2<D>(b1, x);
-    bool v0 = d0 < q.best && !cone_culls<D>(b0, c0, x);
-    bool v1 = d1 < q.best && !cone_culls<D>(b1, c1, x);
-    if (v0 && ch.y > 0) {
-        for (int k = ch.x; k < ch.x + ch.y; ++k) q.best = fminf(q.best, sil_prim_dist2<D>(b.prims, k, x, onp)), stat_prim(s);
-        v0 = false;
+    float key[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const Box<D> bx = n.box(k);
+        const float4 cone = make_float4(comp(cn[0], k), comp(cn[1], k), D == 3 ? comp(cn[D == 3 ? 2 : 0], k) : 0.f,
+                                        comp(cn[D], k));
+        const float d = box_dist2<D>(bx, x);
+        key[k] = d < q.best && !cone_culls<D>(bx, cone, x) ? d : INFINITY;
     }
-    if (v1 && ch.w > 0) {
-        for (int k = ch.z; k < ch.z + ch.w; ++k) q.best = fminf(q.best, sil_prim_dist2<D>(b.prims, k, x, onp)), stat_prim(s);
-        v1 = false;
+    uint32_t lm = leaf_mask(n.ref, [&](int k) { return key[k] < q.best; });
+    while (lm) {
+        const int k = __builtin_ctz(lm);
+        lm &= lm - 1;
+        const int r = comp(n.ref, k);
+        const int f = leaf_first(r), c = leaf_count(r);
+        for (int j = f; j < f + c; ++j) q.best = fminf(q.best, sil_prim_dist2<D>(b.prims, j, x, onp)), stat_prim(s);
     }
-    v0 = v0 && d0 < q.best;
-    v1 = v1 && d1 < q.best;
-    return !trav_next(v0, v1, d0, d1, ch, q.best, q, st);
+    float kk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) kk[k] = comp(n.ref, k) >= 0 && key[k] < q.best ? key[k] : INFINITY;
+    return !trav_next4(kk[0], kk[1], kk[2], kk[3], n.ref, q.best, q, st);
 }
 
 // ----------------------------------------------------------------- rays
@@ -527,36 +590,31 @@ __device__ __forceinline__ bool ray_neumann_step(const DevBvh& b, const float* x
                                                  float back, int skip, RayTrav<D>& q, const LdsStack& st, S* s)
 {
     if (q.t.node < 0) return true;
-    using NodeType = typename NodeT<D>::type;
     const RaySetup<D> ry(x, nu);
-    Box<D> b0, b1;
-    int4 ch;
-    load_node_boxes<D>((const NodeType*)b.nodes, q.t.node, b0, b1, ch);
+    Node4<D> n;
+    load_node4<D>(node_ptr<D>(b.nodes, q.t.node, Layout4<D>::kNeuStride), n);
     stat_node(s);
-    const float e0 = ch.x >= 0 ? ray_box<D>(b0, x, q.inv, -back, q.t.best) : INFINITY;
-    const float e1 = ch.z >= 0 ? ray_box<D>(b1, x, q.inv, -back, q.t.best) : INFINITY;
-    bool v0 = e0 < INFINITY, v1 = e1 < INFINITY;
-    if (v0 && ch.y > 0) {
-        for (int k = ch.x; k < ch.x + ch.y; ++k) {
-            if (k == skip) continue;
-            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+    float key[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        key[k] = comp(n.ref, k) != kEmptyRef ? ray_box<D>(n.box(k), x, q.inv, -back, q.t.best) : INFINITY;
+    uint32_t lm = leaf_mask(n.ref, [&](int k) { return key[k] < INFINITY; });
+    while (lm) {
+        const int k = __builtin_ctz(lm);
+        lm &= lm - 1;
+        const int r = comp(n.ref, k);
+        const int f = leaf_first(r), c = leaf_count(r);
+        for (int j = f; j < f + c; ++j) {
+            if (j == skip) continue;
+            Prim<D> pr; pr.load(b.prims, j); stat_prim(s);
             const float t = pr.ray(ry);
-            if (t < q.t.best && (t > tau || (t > -back && exits<D>(b, k, nu)))) { q.t.best = t; q.t.prim = k; }
+            if (t < q.t.best && (t > tau || (t > -back && exits<D>(b, j, nu)))) { q.t.best = t; q.t.prim = j; }
         }
-        v0 = false;
     }
-    if (v1 && ch.w > 0) {
-        for (int k = ch.z; k < ch.z + ch.w; ++k) {
-            if (k == skip) continue;
-            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-            const float t = pr.ray(ry);
-            if (t < q.t.best && (t > tau || (t > -back && exits<D>(b, k, nu)))) { q.t.best = t; q.t.prim = k; }
-        }
-        v1 = false;
-    }
-    v0 = v0 && e0 < q.t.best;
-    v1 = v1 && e1 < q.t.best;
-    return !trav_next(v0, v1, e0, e1, ch, q.t.best, q.t, st);
+    float kk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) kk[k] = comp(n.ref, k) >= 0 && key[k] < q.t.best ? key[k] : INFINITY;
+    return !trav_next4(kk[0], kk[1], kk[2], kk[3], n.ref, q.t.best, q.t, st);
 }
 
 // ---- visibility: does a Neumann primitive other than `skip` cross the ray
@@ -567,34 +625,32 @@ __device__ __forceinline__ bool visible_neumann_step(const DevBvh& b, const floa
                                                      int skip, RayTrav<D>& q, const LdsStack& st, S* s)
 {
     if (q.t.node < 0) return true;
-    using NodeType = typename NodeT<D>::type;
     const RaySetup<D> ry(x, nu);
     const float tmax = q.t.best;
-    Box<D> b0, b1;
-    int4 ch;
-    load_node_boxes<D>((const NodeType*)b.nodes, q.t.node, b0, b1, ch);
+    Node4<D> n;
+    load_node4<D>(node_ptr<D>(b.nodes, q.t.node, Layout4<D>::kNeuStride), n);
     stat_node(s);
-    bool v0 = ch.x >= 0 && ray_box<D>(b0, x, q.inv, 0.f, tmax) < INFINITY;
-    bool v1 = ch.z >= 0 && ray_box<D>(b1, x, q.inv, 0.f, tmax) < INFINITY;
-    if (v0 && ch.y > 0) {
-        for (int k = ch.x; k < ch.x + ch.y; ++k) {
-            if (k == skip) continue;
-            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
+    float key[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        key[k] = comp(n.ref, k) != kEmptyRef ? ray_box<D>(n.box(k), x, q.inv, 0.f, tmax) : INFINITY;
+    uint32_t lm = leaf_mask(n.ref, [&](int k) { return key[k] < INFINITY; });
+    while (lm) {
+        const int k = __builtin_ctz(lm);
+        lm &= lm - 1;
+        const int r = comp(n.ref, k);
+        const int f = leaf_first(r), c = leaf_count(r);
+        for (int j = f; j < f + c; ++j) {
+            if (j == skip) continue;
+            Prim<D> pr; pr.load(b.prims, j); stat_prim(s);
             const float t = pr.ray(ry);
-            if (t > t_lo && t < tmax) { q.t.prim = k; q.t.node = -1; return true; }
+            if (t > t_lo && t < tmax) { q.t.prim = j; q.t.node = -1; return true; }
         }
-        v0 = false;
     }
-    if (v1 && ch.w > 0) {
-        for (int k = ch.z; k < ch.z + ch.w; ++k) {
-            if (k == skip) continue;
-            Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
-            const float t = pr.ray(ry);
-            if (t > t_lo && t < tmax) { q.t.prim = k; q.t.node = -1; return true; }
-        }
-        v1 = false;
-    }
-    return !trav_next(v0, v1, 0.f, 0.f, ch, INFINITY, q.t, st);
+    float kk[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) kk[k] = comp(n.ref, k) >= 0 ? key[k] : INFINITY;
+    return !trav_next4(kk[0], kk[1], kk[2], kk[3], n.ref, INFINITY, q.t, st);
 }
 
 // ----------------------------------------------------------------- Neumann sample
@@ -625,51 +681,60 @@ template <int D, class S>
 __device__ __forceinline__ bool sample_neumann_step(const DevBvh& b, const float* x, float r, SampleTrav& q, S* s)
 {
     if (q.node < 0) return true;
-    using NodeType = typename NodeT<D>::type;
     const float r2 = r * r;
-    Box<D> b0, b1;
-    int4 ch;
-    float4 a0, a1;
-    load_node((const NodeType*)b.nodes, q.node, b0, b1, ch, a0, a1);
+    const float4* p = node_ptr<D>(b.nodes, q.node, Layout4<D>::kNeuStride);
+    Node4<D> n;
+    load_node4<D>(p, n);
+    const float4 meas = p[Layout4<D>::kAux];
     stat_node(s);
-    const float w0 = box_dist2<D>(b0, x) < r2 ? a0.x : 0.f;
-    const float w1 = box_dist2<D>(b1, x) < r2 ? a1.x : 0.f;
-    const float W = w0 + w1;
-    if (!(W > 0.f)) { q.node = -1; return true; }
-    const float p0 = w0 / W;
-    int c, n;
-    float u = q.u;
-    if (u < p0) {
-        c = ch.x; n = ch.y; q.P *= p0;
-        u = u / p0;
-    } else {
-        c = ch.z; n = ch.w; q.P *= (1.f - p0);
-        u = (u - p0) / (1.f - p0);
+    // children whose box misses the ball get weight 0 (empty children have
+    // an empty box and measure 0)
+    float w[4], W = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        w[k] = box_dist2<D>(n.box(k), x) < r2 ? comp(meas, k) : 0.f;
+        W += w[k];
     }
-    u = fminf(fmaxf(u, 0.f), 0.99999994f);
+    if (!(W > 0.f)) { q.node = -1; return true; }
+    // child k with probability w_k / W: the first whose running sum exceeds
+    // u W (the last positive one if rounding leaves none)
+    const float t = q.u * W;
+    float lo = 0.f, acc = 0.f, wk = 0.f;
+    int ck = 0;
+    bool found = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float a0 = acc;
+        acc += w[k];
+        if (w[k] > 0.f && !found) { ck = k; lo = a0; wk = w[k]; found = t < acc; }
+    }
+    q.P *= wk / W;
+    const float u = fminf(fmaxf((t - lo) / wk, 0.f), 0.99999994f);
     q.u = u;
-    if (n == 0) { q.node = c; return false; }
+    const int rf = comp(n.ref, ck);
+    if (rf >= 0) { q.node = rf; return false; }
+    const int c = leaf_first(rf), nn = leaf_count(rf);
     // leaf: measure-weighted choice among primitives meeting the ball
     q.node = -1;
     float tot = 0.f;
-    for (int k = c; k < c + n; ++k) {
+    for (int k = c; k < c + nn; ++k) {
         Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
         float z[D];
         if (pr.closest(x, z) < r2) tot += b.pextra[k].w;
     }
     if (!(tot > 0.f)) return true;
     const float target = u * tot;
-    float acc = 0.f;
+    float acc2 = 0.f;
     int sel = -1;
     float wsel = 0.f;
-    for (int k = c; k < c + n; ++k) {
+    for (int k = c; k < c + nn; ++k) {
         Prim<D> pr; pr.load(b.prims, k); stat_prim(s);
         float z[D];
         if (!(pr.closest(x, z) < r2)) continue;
-        const float w = b.pextra[k].w;
-        sel = k; wsel = w;
-        acc += w;
-        if (target < acc) break;
+        const float wj = b.pextra[k].w;
+        sel = k; wsel = wj;
+        acc2 += wj;
+        if (target < acc2) break;
     }
     q.prim = sel;
     q.prob = q.P * (wsel / tot);

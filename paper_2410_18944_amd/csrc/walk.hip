@@ -77,11 +77,11 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 // LDS bytes of one walk workgroup: the traversal stack and the guide's output
 // transpose are used in different phases of a step and share the space.  A
-// traversal keeps at most one deferred child per internal level of the path it
-// is on, so the stack needs (deepest hierarchy's depth) entries; one spare.
-static inline size_t walk_lds_bytes(bool guided, int max_depth, int out_stride)
+// traversal defers at most three children per level of the path it is on;
+// the builder reports the entries the deepest hierarchy needs.
+static inline size_t walk_lds_bytes(bool guided, int stack_entries, int out_stride)
 {
-    const size_t stack = sizeof(uint2) * (size_t)(max_depth + 1) * kWave;
+    const size_t stack = sizeof(uint2) * (size_t)stack_entries * kWave;
     const size_t gout = guided ? sizeof(float) * kWave * (size_t)out_stride : 0;
     return stack > gout ? stack : gout;
 }
@@ -1045,7 +1045,7 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
         if (P.cost) fn = guided ? walk_kernel3g<true> : walk_kernel3u<true>;
         else fn = guided ? walk_kernel3g<false> : walk_kernel3u<false>;
     }
-    const size_t lds = walk_lds_bytes(guided, geom->max_depth, guide_out_stride(P.guide));
+    const size_t lds = walk_lds_bytes(guided, geom->stack_entries, guide_out_stride(P.guide));
     int per_cu = g_waves_per_cu;
     if (per_cu == 0) {
         int nb = 0;

@@ -8,34 +8,39 @@
 
 namespace wost {
 
-constexpr int kMaxStack = 24;      // traversal stack entries per lane (LDS)
-constexpr int kMaxDepth = kMaxStack - 1;
+constexpr int kMaxStack = 40;      // traversal stack entries per lane (LDS)
 constexpr int kWave = 64;
 
-// Binary BVH node holding both children's boxes, so one fetch decides the
-// visit order.  ch = (c0, n0, c1, n1): n_i > 0 -> leaf with primitives
-// [c_i, c_i + n_i); n_i == 0 && c_i >= 0 -> inner node c_i; c_i < 0 -> empty.
-// aux_i: Neumann hierarchy -> (subtree measure, 0, 0, 0);
-//        silhouette hierarchy -> (cone axis xyz (2D: xy,0), half angle).
-struct alignas(16) Node2 {
-    float4 b0;      // lo.x lo.y hi.x hi.y
-    float4 b1;
-    int4 ch;
-    float4 aux0;
-    float4 aux1;
-};
-struct alignas(16) Node3 {
-    float4 b0a;     // lo0.xyz hi0.x
-    float4 b0b;     // hi0.yz lo1.xy
-    float4 b1b;     // lo1.z hi1.xyz
-    int4 ch;
-    float4 aux0;
-    float4 aux1;
+// Four-wide BVH node: the four children of a node are stored as structure of
+// arrays, one float4 per coordinate, so a single node fetch tests all four.
+// Node i of a hierarchy is the run of float4 at nodes + i * stride:
+//   [0, D)       lo.x, lo.y (, lo.z) of children 0..3
+//   [D, 2D)      hi.x, hi.y (, hi.z)
+//   2D           int4 child references (bit patterns):
+//                  >= 0          inner child: node index
+//                  kEmptyRef     no child (its box is empty and never tested)
+//                  other < 0     leaf: -1 - (first * 64 + count - 1),
+//                                primitives [first, first + count), count <= 64
+//   2D + 1 ...   per-hierarchy child data:
+//                  Dirichlet     none                          stride 2D + 1
+//                  Neumann       subtree measure (1 float4)    stride 2D + 2
+//                  silhouettes   normal cone axis x, y (, z)
+//                                and cos of its half-angle     stride 3D + 2
+constexpr int32_t kEmptyRef = (int32_t)0x80000000;
+constexpr int kLeafMax = 64;
+constexpr int64_t kMaxLeafFirst = (1ll << 25) - kLeafMax;   // first < this
+
+template <int D> struct Layout4 {
+    static constexpr int kRef = 2 * D;
+    static constexpr int kAux = 2 * D + 1;
+    static constexpr int kDirStride = 2 * D + 1;
+    static constexpr int kNeuStride = 2 * D + 2;
+    static constexpr int kSilStride = 3 * D + 2;
 };
 
-template <int D> struct NodeT;
-template <> struct NodeT<2> { using type = Node2; };
-template <> struct NodeT<3> { using type = Node3; };
+__host__ __device__ inline int32_t leaf_ref(int32_t first, int32_t count) { return -1 - (first * kLeafMax + count - 1); }
+__host__ __device__ inline int32_t leaf_first(int32_t ref) { return (-1 - ref) / kLeafMax; }
+__host__ __device__ inline int32_t leaf_count(int32_t ref) { return (-1 - ref) % kLeafMax + 1; }
 
 // Primitive records.
 //  2D segment: float4 (a.x, a.y, b.x, b.y)
@@ -47,7 +52,7 @@ template <> struct NodeT<3> { using type = Node3; };
 //                 q1, q2 their internal Neumann ids as int bit patterns
 //                 (q2 = -1: boundary feature with a single Neumann neighbour)
 struct DevBvh {
-    const void* nodes;      // NodeT<D>[n_nodes]
+    const float4* nodes;    // n_nodes four-wide nodes (layout above)
     const float4* prims;    // prim records
     const float4* pextra;   // Neumann per-primitive normal + measure (or null)
     const int32_t* orig;    // internal primitive id -> caller primitive index
@@ -77,7 +82,8 @@ struct FieldDev {
 struct wost_geom {
     int32_t dim = 0;
     int64_t n_dir = 0, n_neu = 0, n_sil = 0;
-    int32_t max_depth = 0;
+    int32_t max_depth = 0;          // deepest binary split level (reported)
+    int32_t stack_entries = 0;      // traversal stack entries a lane needs
     double diag = 0;
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     // host image of the device buffer and section offsets (bytes)

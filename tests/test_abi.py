@@ -107,11 +107,27 @@ def test_builder_counts_and_depth(lib, name):
     lib.load().wost_geom_free(h)
 
 
-def test_builder_brute_force_is_single_leaf(lib):
+def test_builder_brute_force_uses_full_leaves(lib):
+    """Brute force packs 64 primitives per leaf (C1: 128 Dirichlet segments ->
+    one split), and every hierarchy needs a short traversal stack."""
     s = scenes.scene_c1()
     rc, h = _build(lib, 2, s.verts, s.prims, s.bc, brute=1)
     assert rc == 0
-    assert _info(lib, h)[4] <= 1
+    info = _info(lib, h)
+    assert info[4] <= int(np.ceil(np.log2(max(info[1], info[2], 1) / 64.0))) + 1
+    assert 1 <= info[7] <= 4
+    lib.load().wost_geom_free(h)
+
+
+@pytest.mark.parametrize("name", ["C2", "cube"])
+def test_builder_stack_entries_cover_four_wide_depth(lib, name):
+    """A four-wide level spans two binary levels and defers at most three
+    children, so the stack needs at most 3 * ceil((depth + 1) / 2) entries."""
+    s = scenes.make_scene(name)
+    rc, h = _build(lib, s.dim, s.verts, s.prims, s.bc)
+    assert rc == 0
+    info = _info(lib, h)
+    assert 1 <= info[7] <= 3 * int(np.ceil((info[4] + 1) / 2.0)) + 1
     lib.load().wost_geom_free(h)
 
 
