@@ -309,10 +309,10 @@ int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin,
  * results. */
 int wost_set_launch(int32_t waves_per_cu);
 /* Walk pool of the persistent kernel.  Each wave keeps `slots_per_wave`
- * walks in flight (a multiple of 64 in [64, 8192]; 0 = default 512) and
+ * walks in flight (a multiple of 64 in [64, 8192]; 0 = default 384) and
  * advances all of them one star per round, query by query; a lane whose
  * query has finished takes the next walk of that query's list, once at least
- * `refill_batch` lanes (1..64; 0 = default 16) are waiting or no lane is
+ * `refill_batch` lanes (1..64; 0 = default 32) are waiting or no lane is
  * still traversing.  Larger pools keep more lanes busy at the cost of
  * workspace.  Process wide; affects throughput and workspace size only,
  * never results.  Call wost_solve_workspace_bytes after changing it. */

@@ -208,8 +208,8 @@ def solve(geom, problem, pts, wpp, seed=18944, walk_offset=0, guide=None, acc=No
 
 
 def set_walk_pool(slots_per_wave=0, refill_batch=0):
-    """Walk slots per persistent wave (multiple of 64; 0 = default 512) and
-    the number of finished lanes that refill together (0 = default 16)."""
+    """Walk slots per persistent wave (multiple of 64; 0 = default 384) and
+    the number of finished lanes that refill together (0 = default 32)."""
     L.check(L.load().wost_set_walk_pool(int(slots_per_wave), int(refill_batch)), "wost_set_walk_pool")
 
 

@@ -65,6 +65,20 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
+__device__ __forceinline__ float wave_sum_f(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
 #pragma unroll
@@ -98,7 +112,8 @@ static inline size_t walk_lds_bytes(bool guided, int stack_entries, int out_stri
 // next walk of that phase's list at once, so the wave does not wait for its
 // slowest lane; lanes of a phase all run the same query code.
 
-enum : int { ST_EMPTY = 0, ST_ACTIVE = 1, ST_STEP = 2, ST_DONE = 3 };
+// ST_VIS: a stepping walk whose Neumann sample waits for its visibility ray
+enum : int { ST_EMPTY = 0, ST_ACTIVE = 1, ST_STEP = 2, ST_DONE = 3, ST_VIS = 4 };
 
 template <int D>
 struct PoolField {
@@ -157,7 +172,8 @@ __device__ __forceinline__ void wave_sync()
 // take new work together: finishing and refilling is far more code than one
 // traversal iteration, and run for a handful of lanes at a time it would cost
 // nearly as much as for all 64.
-static int g_refill_batch = 16;
+constexpr int kDefaultRefillBatch = 32;
+static int g_refill_batch = kDefaultRefillBatch;
 
 // One traversal phase over list[0, n) with refill from the list: init(slot)
 // loads a walk's query, step() advances it by one node and returns true when
@@ -402,7 +418,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
         {
             float x[D];
             Trav q;
-            run_phase(L_act, n_act, L_step, n_step, lane, batch, witer[0],
+            run_phase(L_act, n_act, (int32_t*)nullptr, dummy_n, lane, batch, witer[0],
                 [&](int slot) {
                     const uint32_t g = base + slot;
 #pragma unroll
@@ -434,6 +450,41 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                     pv.i(F::STAT, g) = ST_STEP;
                     return true;
                 });
+        }
+        wave_sync();
+        // the walks that step on, in two groups: first those whose star
+        // queries are likely long (far from the Dirichlet boundary, or on
+        // the Neumann boundary, where normal cones prune little), then the
+        // rest; each group in slot order.  A phase hands out its list in
+        // order, so long queries start early instead of trailing at the end
+        // of the phase while the other lanes idle, and neighbouring lanes
+        // read neighbouring slots.
+        {
+            float ksum = 0.f;
+            int kn = 0;
+            for (int c0 = 0; c0 < N; c0 += kWave) {
+                const uint32_t g = base + c0 + lane;
+                if (pv.i(F::STAT, g) == ST_STEP) {
+                    ksum += pv.f(F::DD, g) * (pv.i(F::ONP, g) >= 0 ? 4.f : 1.f);
+                    ++kn;
+                }
+            }
+            const float thr = wave_sum_f(ksum) / fmaxf((float)wave_sum_i(kn), 1.f);
+#pragma unroll
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int c0 = 0; c0 < N; c0 += kWave) {
+                    const int li = c0 + lane;
+                    const uint32_t g = base + li;
+                    bool stp = pv.i(F::STAT, g) == ST_STEP;
+                    if (stp) {
+                        const bool longq = pv.f(F::DD, g) * (pv.i(F::ONP, g) >= 0 ? 4.f : 1.f) >= thr;
+                        stp = pass == 0 ? longq : !longq;
+                    }
+                    const uint64_t m = __ballot(stp);
+                    if (stp) L_step[n_step + (int)lane_prefix(m)] = li;
+                    n_step += __popcll(m);
+                }
+            }
         }
         wave_sync();
         if (n_step == 0) continue;
@@ -524,7 +575,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             {
                 float x[D], r = 0.f, u1 = 0.f, u2 = 0.f;
                 SampleTrav q;
-                run_phase(L_step, n_step, L_vis, n_vis, lane, batch, witer[2],
+                run_phase(L_step, n_step, (int32_t*)nullptr, dummy_n, lane, batch, witer[2],
                     [&](int slot) {
                         const uint32_t g = base + slot;
 #pragma unroll
@@ -562,8 +613,18 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                         pv.f(F::NVAL, g) = green_ball<D>(r, rho) * hv * (ex.w / q.prob) * inv_alpha;
 #pragma unroll
                         for (int i = 0; i < D; ++i) pv.f(F::Z + i, g) = z[i];
-                        return true;
+                        pv.i(F::STAT, g) = ST_VIS;
+                        return false;
                     });
+            }
+            wave_sync();
+            // visibility candidates in slot order (see the stepping list)
+            for (int c0 = 0; c0 < N; c0 += kWave) {
+                const int li = c0 + lane;
+                const bool vis = pv.i(F::STAT, base + li) == ST_VIS;
+                const uint64_t m = __ballot(vis);
+                if (vis) L_vis[n_vis + (int)lane_prefix(m)] = li;
+                n_vis += __popcll(m);
             }
             wave_sync();
             if (n_vis > 0) {
@@ -589,10 +650,9 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                     },
                     [&]() { return visible_neumann_step<D>(G.neu, xo, dn, 0.f, onp, q, st, &sq[3]); },
                     [&](int slot) {
-                        if (q.t.prim < 0) {
-                            const uint32_t g = base + slot;
-                            pv.f(F::CON, g) += pv.f(F::NVAL, g);
-                        }
+                        const uint32_t g = base + slot;
+                        if (q.t.prim < 0) pv.f(F::CON, g) += pv.f(F::NVAL, g);
+                        pv.i(F::STAT, g) = ST_STEP;
                         return false;
                     });
                 wave_sync();
@@ -897,7 +957,8 @@ static bool copy_field(const wost_field& in, int dim, FieldDev& out, const char*
 
 using namespace wost;
 
-static int g_pool_n = 512;   // walk slots per wave
+constexpr int kDefaultPoolSlots = 384;
+static int g_pool_n = kDefaultPoolSlots;   // walk slots per wave
 #ifndef WOST_POOL_MIN
 #define WOST_POOL_MIN 64
 #endif
@@ -934,8 +995,8 @@ extern "C" int64_t wost_solve_workspace_bytes(const wost_geom* geom, int64_t n_p
 
 extern "C" int wost_set_walk_pool(int32_t slots_per_wave, int32_t refill_batch)
 {
-    if (slots_per_wave == 0) slots_per_wave = 512;
-    if (refill_batch == 0) refill_batch = 16;
+    if (slots_per_wave == 0) slots_per_wave = kDefaultPoolSlots;
+    if (refill_batch == 0) refill_batch = kDefaultRefillBatch;
     if (slots_per_wave < 64 || slots_per_wave > 8192 || slots_per_wave % 64) {
         set_error("wost_set_walk_pool: slots_per_wave must be a multiple of 64 in [64, 8192] (0 = default)");
         return WOST_EINVAL;
