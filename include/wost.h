@@ -117,6 +117,10 @@ void wost_geom_free(wost_geom* geom);
 
 /* Batched geometric queries of the walk (for inspection and parity tests).
  *   pts          device [n][dim]
+ *   on_prim      device [n] or NULL: caller index of the Neumann primitive each
+ *                point lies on (-1 = none); such a primitive faces its point
+ *                from the front in the silhouette query, as for a walker
+ *                standing on it (Sec. 3.2)
  *   d_dir, xbar  device [n], [n][dim]: distance to / closest point on the
  *                Dirichlet boundary (Sec. 3.2 epsilon-shell test); NULL to skip
  *   d_sil        device [n]: distance to the closest Neumann silhouette point
@@ -125,9 +129,9 @@ void wost_geom_free(wost_geom* geom);
  *                ray_t [n] and ray_prim [n] (caller primitive index, -1 = miss)
  *                gives the first Neumann hit in (tau, tmax); NULL to skip.
  * Missing results are +inf. */
-int wost_query(const wost_geom* geom, const float* pts, int64_t n, float* d_dir, float* xbar,
-               float* d_sil, const float* ray_dir, const float* ray_tmax, float* ray_t,
-               int32_t* ray_prim, void* stream);
+int wost_query(const wost_geom* geom, const float* pts, int64_t n, const int32_t* on_prim,
+               float* d_dir, float* xbar, float* d_sil, const float* ray_dir, const float* ray_tmax,
+               float* ray_t, int32_t* ray_prim, void* stream);
 
 /* ------------------------------------------------------------ problem + solve */
 #define WOST_SAMPLING_UNIFORM 0      /* original WoSt: uniform directions (c = 0)       */

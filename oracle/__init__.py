@@ -69,7 +69,7 @@ def _load():
     lib.or_walk_trace.argtypes = [P, C.POINTER(_Problem), dp, C.c_uint64, C.c_uint32, C.c_uint32,
                                   dp, dp, C.c_int32, dp, dp, C.POINTER(C.c_int32)]
     lib.or_closest_dirichlet.argtypes = [P, dp, C.c_int64, dp, dp]
-    lib.or_silhouette.argtypes = [P, dp, C.c_int64, dp]
+    lib.or_silhouette.argtypes = [P, dp, C.c_int64, C.POINTER(C.c_int64), dp]
     lib.or_ray_neumann.argtypes = [P, dp, dp, dp, C.c_int64, dp, C.POINTER(C.c_int64)]
     lib.or_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
     lib.or_philox4x32_10_batch.argtypes = [C.POINTER(C.c_uint32), C.c_int64, C.POINTER(C.c_uint32),
@@ -221,10 +221,14 @@ class OracleScene:
                                      _ptr(xb, C.c_double))
         return d, xb
 
-    def silhouette(self, x):
+    def silhouette(self, x, on_prim=None):
+        """on_prim: optional per-point primitive index the point lies on (-1 =
+        none); that primitive then faces its point from the front."""
         x = np.ascontiguousarray(x, np.float64)
         d = np.zeros(x.shape[0])
-        _load().or_silhouette(self.h, _ptr(x, C.c_double), x.shape[0], _ptr(d, C.c_double))
+        op = None if on_prim is None else np.ascontiguousarray(on_prim, np.int64)
+        _load().or_silhouette(self.h, _ptr(x, C.c_double), x.shape[0],
+                              None if op is None else _ptr(op, C.c_int64), _ptr(d, C.c_double))
         return d
 
     def ray_neumann(self, x, nu, tmax):

@@ -327,14 +327,18 @@ static int is_front(const or_scene* s, int64_t q, const double* x)
     return -dot(d, w, s->n_out + q * d) >= -s->tau;
 }
 
-/* distance to the nearest Neumann silhouette point seen from x (exhaustive) */
-double or_silhouette_one(const or_scene* s, const double* x)
+/* distance to the nearest Neumann silhouette point seen from x (exhaustive),
+   Sec. 3.2: a candidate is a silhouette when its adjacent Neumann primitives
+   face x differently.  `own` (or -1) is a primitive x is known to lie on: it
+   faces x from the front whatever the rounding of x (the walker's own
+   primitive, as for a walker standing on the boundary) */
+double or_silhouette_one(const or_scene* s, const double* x, int64_t own)
 {
     double best = INFINITY, tmp[3];
     const int d = s->dim;
     for (int64_t k = 0; k < s->n_sil; ++k) {
         int32_t q0 = s->sil_adj[2 * k], q1 = s->sil_adj[2 * k + 1];
-        int sil = (q1 < 0) ? 1 : (is_front(s, q0, x) != is_front(s, q1, x));
+        int sil = (q1 < 0) ? 1 : ((q0 == own || is_front(s, q0, x)) != (q1 == own || is_front(s, q1, x)));
         if (!sil) continue;
         const double* P = s->sil_p + k * 2 * d;
         double dd = (d == 2) ? sqrt((x[0] - P[0]) * (x[0] - P[0]) + (x[1] - P[1]) * (x[1] - P[1]))
@@ -484,7 +488,7 @@ static or_walk_result walk_one(const or_scene* s, const or_problem* pb, const do
             res.status = (dD <= pb->eps) ? 0 : 1;
             break;
         }
-        double dS = or_silhouette_one(s, x);
+        double dS = or_silhouette_one(s, x, -1);
         double r = fmin(dD, dS);
         if (r < pb->r_min) r = pb->r_min;
         const double alpha = onN ? 0.5 : 1.0;
@@ -644,10 +648,11 @@ void or_closest_dirichlet(const or_scene* s, const double* x, int64_t n, double*
         dist[i] = or_closest_dirichlet_one(s, x + i * s->dim, xbar + i * s->dim, NULL);
 }
 
-void or_silhouette(const or_scene* s, const double* x, int64_t n, double* dist)
+/* on_prim: NULL, or per point the caller primitive it lies on (-1 = none) */
+void or_silhouette(const or_scene* s, const double* x, int64_t n, const int64_t* on_prim, double* dist)
 {
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) dist[i] = or_silhouette_one(s, x + i * s->dim);
+    for (int64_t i = 0; i < n; ++i) dist[i] = or_silhouette_one(s, x + i * s->dim, on_prim ? on_prim[i] : -1);
 }
 
 void or_ray_neumann(const or_scene* s, const double* x, const double* nu, const double* tmax,

@@ -84,7 +84,7 @@ class Geometry:
             lib.wost_geom_free(self.h)
             self.h = None
 
-    def query(self, pts, dirichlet=True, silhouette=True, ray_dir=None, ray_tmax=None):
+    def query(self, pts, dirichlet=True, silhouette=True, ray_dir=None, ray_tmax=None, on_prim=None):
         lib = L.load()
         pts = pts.contiguous()
         n = pts.shape[0]
@@ -99,7 +99,9 @@ class Geometry:
             ray_tmax = torch.as_tensor(ray_tmax, dtype=torch.float32, device=dev).expand(n).contiguous()
             ray_t = torch.empty(n, dtype=torch.float32, device=dev)
             ray_prim = torch.empty(n, dtype=torch.int32, device=dev)
-        L.check(lib.wost_query(self.h, _ptr(pts), n, _ptr(d_dir), _ptr(xbar), _ptr(d_sil), _ptr(ray_dir),
+        if on_prim is not None:
+            on_prim = torch.as_tensor(on_prim, dtype=torch.int32, device=dev).contiguous()
+        L.check(lib.wost_query(self.h, _ptr(pts), n, _ptr(on_prim), _ptr(d_dir), _ptr(xbar), _ptr(d_sil), _ptr(ray_dir),
                                _ptr(ray_tmax), _ptr(ray_t), _ptr(ray_prim), _stream()), "wost_query")
         if dirichlet:
             out.update(d_dir=d_dir, xbar=xbar)

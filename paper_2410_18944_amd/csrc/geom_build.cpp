@@ -139,6 +139,8 @@ struct Sil {
     double n1[3], n2[3];    // inward normals of adjacent Neumann prims; n2 = 0 if boundary
     bool boundary;
     int64_t q1, q2;         // adjacent Neumann primitives (caller ids); q2 = -1 if boundary
+    int64_t v;              // 2D: vertex id
+    int32_t piece;          // convex piece the vertex is interior to, or -1
 };
 
 inline double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -190,9 +192,12 @@ wost::DevGeom wost_geom::devgeom() const
         b[i]->prims = (const float4*)(base + sec[i].prims);
         b[i]->pextra = sec[i].pextra >= 0 ? (const float4*)(base + sec[i].pextra) : nullptr;
         b[i]->orig = sec[i].orig >= 0 ? (const int32_t*)(base + sec[i].orig) : nullptr;
+        b[i]->piece = sec[i].piece >= 0 ? (const int32_t*)(base + sec[i].piece) : nullptr;
         b[i]->n_nodes = sec[i].n_nodes;
         b[i]->n_prims = sec[i].n_prims;
     }
+    g.neu_id = off_neu_id >= 0 ? (const int32_t*)(base + off_neu_id) : nullptr;
+    g.n_caller = n_caller;
     g.dim = dim;
     g.diag = (float)diag;
     g.tau = (float)(1e-6 * diag);
@@ -299,8 +304,75 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
             s.q1 = L[0];
             s.q2 = s.boundary ? -1 : L[1];
             for (int i = 0; i < 3; ++i) s.n2[i] = s.boundary ? 0.0 : -nout[L[1]][i];
+            s.v = va;
+            s.piece = -1;
             sils.push_back(s);
         }
+    }
+    // ---- convex pieces (2D): maximal runs of Neumann segments joined at
+    // strictly convex vertices, cut so that each run turns by less than
+    // 0.9 pi.  Such a run is the graph of a convex function over some
+    // direction and lies on the domain side of every one of its segments'
+    // lines, so seen from a point on one of its segments every segment of
+    // the run faces front and no vertex interior to it is a silhouette.
+    std::vector<int32_t> seg_piece(n_prims, -1);
+    if (d == 2) {
+        std::vector<std::vector<int64_t>> inc(n_verts);
+        for (int64_t q = 0; q < n_prims; ++q)
+            if (bc[q])
+                for (int k = 0; k < 2; ++k) inc[prims[q * 2 + k]].push_back(q);
+        auto other_end = [&](int64_t q, int64_t v) { return prims[q * 2] == v ? prims[q * 2 + 1] : prims[q * 2]; };
+        std::vector<char> join(n_verts, 0);
+        std::vector<double> turn(n_verts, 0.0);
+        for (int64_t v = 0; v < n_verts; ++v) {
+            if (inc[v].size() != 2) continue;
+            const int64_t s1 = inc[v][0], s2 = inc[v][1];
+            const int64_t p1 = other_end(s1, v), p2 = other_end(s2, v);
+            if (p1 == v || p2 == v) continue;
+            double e1[2], e2[2];
+            for (int i = 0; i < 2; ++i) {
+                e1[i] = (double)verts[p1 * 2 + i] - verts[v * 2 + i];
+                e2[i] = (double)verts[p2 * 2 + i] - verts[v * 2 + i];
+            }
+            const double l1 = std::hypot(e1[0], e1[1]), l2 = std::hypot(e2[0], e2[1]);
+            // sine of the turn, measured against each inward normal
+            const double c1 = -(e2[0] * nout[s1][0] + e2[1] * nout[s1][1]) / l2;
+            const double c2 = -(e1[0] * nout[s2][0] + e1[1] * nout[s2][1]) / l1;
+            if (!(c1 > 1e-6 && c2 > 1e-6)) continue;
+            join[v] = 1;
+            turn[v] = std::acos(std::max(-1.0, std::min(1.0, -(e1[0] * e2[0] + e1[1] * e2[1]) / (l1 * l2))));
+        }
+        const double limit = 0.9 * M_PI;
+        int32_t n_pieces = 0;
+        for (int64_t q0 = 0; q0 < n_prims; ++q0) {
+            if (!bc[q0] || seg_piece[q0] >= 0) continue;
+            // back up to the first segment of the run (or stay on q0 for a
+            // closed convex loop)
+            int64_t cur = q0, v = prims[q0 * 2];
+            for (int64_t guard = 0; guard < n_prims && join[v]; ++guard) {
+                const int64_t prv = inc[v][0] == cur ? inc[v][1] : inc[v][0];
+                if (prv == q0 || seg_piece[prv] >= 0) break;
+                cur = prv;
+                v = other_end(prv, v);
+            }
+            // walk forward, starting a new piece whenever the turn would
+            // reach the limit
+            int32_t pc = n_pieces++;
+            double acc = 0.0;
+            seg_piece[cur] = pc;
+            v = other_end(cur, v);
+            for (int64_t guard = 0; guard < n_prims && join[v]; ++guard) {
+                const int64_t nxt = inc[v][0] == cur ? inc[v][1] : inc[v][0];
+                if (seg_piece[nxt] >= 0) break;
+                if (acc + turn[v] >= limit) { pc = n_pieces++; acc = 0.0; }
+                else acc += turn[v];
+                seg_piece[nxt] = pc;
+                cur = nxt;
+                v = other_end(nxt, v);
+            }
+        }
+        for (auto& sl : sils)
+            if (!sl.boundary && join[sl.v] && seg_piece[sl.q1] == seg_piece[sl.q2]) sl.piece = seg_piece[sl.q1];
     }
     // ---- hierarchies
     wost_geom* g = new wost_geom();
@@ -376,9 +448,22 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
         std::vector<double> node_meas(nn, 0.0);
         std::vector<std::vector<std::array<double, 3>>> node_normals(which == 2 ? nn : 0);
         std::vector<char> node_has_boundary(nn, 0);
+        // convex piece shared by every candidate of a subtree, or -1
+        std::vector<int32_t> sub_piece(nn * 2, -1), node_piece(nn, -1);
+        auto join_piece = [](int32_t a, int32_t b) { return a == -2 ? b : (b == -2 ? a : (a == b ? a : -1)); };
         for (int ni = nn - 1; ni >= 0; --ni) {
             const BuiltNode& nd = B.nodes[ni];
+            int32_t np_acc = -2;
             for (int ch = 0; ch < 2; ++ch) {
+                if (which == 2) {
+                    int32_t pc = -2;
+                    if (nd.n[ch] > 0)
+                        for (int k = nd.c[ch]; k < nd.c[ch] + nd.n[ch]; ++k) pc = join_piece(pc, sils[B.order[k]].piece);
+                    else if (nd.c[ch] >= 0)
+                        pc = node_piece[nd.c[ch]];
+                    sub_piece[ni * 2 + ch] = pc == -2 ? -1 : pc;
+                    np_acc = join_piece(np_acc, pc);
+                }
                 double m = 0;
                 std::vector<std::array<double, 3>> normals;
                 bool bnd = false;
@@ -414,6 +499,7 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
                     node_has_boundary[ni] = node_has_boundary[ni] || bnd;
                 }
             }
+            if (which == 2) node_piece[ni] = np_acc == -2 ? -1 : np_acc;
             if (which == 2) {
                 // keep memory bounded: children's lists are no longer needed
                 for (int ch = 0; ch < 2; ++ch)
@@ -492,12 +578,12 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
             delete g;
             return WOST_EUNSUPPORTED;
         }
-        const int stride = which == 0 ? 2 * d + 1 : which == 1 ? 2 * d + 2 : 3 * d + 2;
+        const int stride = which == 0 ? 2 * d + 1 : which == 1 ? 2 * d + 2 : 3 * d + 3;
         const Box all_box = B.range_box(0, (int)items.size());
         std::vector<float4> nodes4((size_t)n4 * stride);
         for (int i = 0; i < n4; ++i) {
             float lo[3][4], hi[3][4], aux[4][4];
-            int32_t ref[4];
+            int32_t ref[4], pcs[4] = {-1, -1, -1, -1};
             for (int k = 0; k < 4; ++k) {
                 for (int a = 0; a < 3; ++a) { lo[a][k] = INFINITY; hi[a][k] = -INFINITY; }
                 for (int a = 0; a < 4; ++a) aux[a][k] = 0.f;
@@ -514,6 +600,7 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
                     const float v[4] = {ax.x, ax.y, ax.z, ax.w};
                     for (int a = 0; a < d; ++a) aux[a][k] = v[a];
                     aux[d][k] = v[3];
+                    pcs[k] = brute ? -1 : sub_piece[en.bn * 2 + en.ch];
                 }
             }
             float4* o = &nodes4[(size_t)i * stride];
@@ -525,6 +612,10 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
             memcpy(&o[2 * d], &r, sizeof(r));
             const int n_aux = which == 1 ? 1 : which == 2 ? d + 1 : 0;
             for (int a = 0; a < n_aux; ++a) o[2 * d + 1 + a] = make_float4(aux[a][0], aux[a][1], aux[a][2], aux[a][3]);
+            if (which == 2) {
+                const int4 pv = make_int4(pcs[0], pcs[1], pcs[2], pcs[3]);
+                memcpy(&o[3 * d + 2], &pv, sizeof(pv));
+            }
         }
         // validation of the four-wide references (the kernels index without checks)
         {
@@ -589,7 +680,15 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
         int64_t off_prims = push_bytes(img, pr.data(), pr.size());
         int64_t off_px = which == 1 ? push_bytes(img, px.data(), px.size()) : -1;
         int64_t off_orig = which < 2 ? push_bytes(img, orig.data(), orig.size()) : -1;
-        g->sec[which] = {off_nodes, off_prims, off_px, off_orig, n4, np};
+        int64_t off_piece = -1;
+        if (which == 2) {
+            // convex piece of every Neumann primitive, by internal id
+            std::vector<int32_t> pc(std::max<int64_t>(g->n_neu, 1), -1);
+            for (int64_t q = 0; q < n_prims; ++q)
+                if (bc[q] && neu_internal[q] >= 0) pc[neu_internal[q]] = brute ? -1 : seg_piece[q];
+            off_piece = push_bytes(img, pc.data(), pc.size());
+        }
+        g->sec[which] = {off_nodes, off_prims, off_px, off_orig, off_piece, n4, np};
         if (which == 0) g->n_dir = np;
         if (which == 1) {
             g->n_neu = np;
@@ -598,6 +697,8 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
         if (which == 2) g->n_sil = np;
         if (which < 2) orig_all.insert(orig_all.end(), orig.begin(), orig.end());
     }
+    g->off_neu_id = push_bytes(img, neu_internal.data(), neu_internal.size());
+    g->n_caller = n_prims;
     img.resize((img.size() + 255) & ~size_t(255));
     g->bytes = (int64_t)img.size();
     g->image = (uint8_t*)malloc(img.size());

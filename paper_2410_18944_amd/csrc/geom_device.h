@@ -495,10 +495,14 @@ __device__ __forceinline__ float sil_prim_dist2(const float4* p, int k, const fl
     return closest_seg<D>(x, a, e, c);
 }
 
-// ---- closest silhouette: q.best = squared distance (starts at the bound)
+// ---- closest silhouette: q.best = squared distance (starts at the bound).
+// `piece` is the convex piece of the Neumann primitive the walker stands on
+// (-1 off the boundary or outside any piece): no candidate interior to that
+// piece is a silhouette from x, so children holding only such candidates are
+// skipped.
 template <int D, class S>
-__device__ __forceinline__ bool closest_silhouette_step(const DevBvh& b, const float* x, int onp, Trav& q,
-                                                        const LdsStack& st, S* s)
+__device__ __forceinline__ bool closest_silhouette_step(const DevBvh& b, const float* x, int onp, int piece,
+                                                        Trav& q, const LdsStack& st, S* s)
 {
     if (q.node < 0) return true;
     const float4* p = node_ptr<D>(b.nodes, q.node, Layout4<D>::kSilStride);
@@ -507,6 +511,8 @@ __device__ __forceinline__ bool closest_silhouette_step(const DevBvh& b, const f
     float4 cn[D + 1];
 #pragma unroll
     for (int a = 0; a <= D; ++a) cn[a] = p[Layout4<D>::kAux + a];
+    const float4 pf = p[Layout4<D>::kPiece];
+    const int4 pcs = make_int4(__float_as_int(pf.x), __float_as_int(pf.y), __float_as_int(pf.z), __float_as_int(pf.w));
     stat_node(s);
     float key[4];
 #pragma unroll
@@ -515,7 +521,8 @@ __device__ __forceinline__ bool closest_silhouette_step(const DevBvh& b, const f
         const float4 cone = make_float4(comp(cn[0], k), comp(cn[1], k), D == 3 ? comp(cn[D == 3 ? 2 : 0], k) : 0.f,
                                         comp(cn[D], k));
         const float d = box_dist2<D>(bx, x);
-        key[k] = d < q.best && !cone_culls<D>(bx, cone, x) ? d : INFINITY;
+        const bool own = piece >= 0 && comp(pcs, k) == piece;
+        key[k] = d < q.best && !own && !cone_culls<D>(bx, cone, x) ? d : INFINITY;
     }
     uint32_t lm = leaf_mask(n.ref, [&](int k) { return key[k] < q.best; });
     while (lm) {
@@ -767,7 +774,8 @@ __device__ float closest_silhouette(const DevBvh& b, const float* x, float best2
 {
     Trav q;
     trav_begin(b, best2, q);
-    while (!closest_silhouette_step<D>(b, x, onp, q, st, s)) {}
+    const int piece = onp >= 0 && b.piece ? b.piece[onp] : -1;
+    while (!closest_silhouette_step<D>(b, x, onp, piece, q, st, s)) {}
     return q.best;
 }
 

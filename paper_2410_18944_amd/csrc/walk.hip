@@ -223,6 +223,43 @@ __device__ __forceinline__ void run_phase(const int32_t* list, int n, int32_t* o
     }
 }
 
+// List the pool slots selected by in(g) in two groups: first those whose
+// key(g) is at least the mean key of the selected slots, then the rest, each
+// group in slot order.  The keys predict how long a walk's next query runs;
+// a phase hands its list out in order, so long queries start early instead of
+// trailing at the end of the phase while the other lanes idle, and
+// neighbouring lanes read neighbouring slots.  Returns the list length.
+template <class In, class Key>
+__device__ __forceinline__ int list_long_first(int32_t* L, int N, uint32_t base, int lane, In&& in, Key&& key)
+{
+    float ksum = 0.f;
+    int kn = 0;
+    for (int c0 = 0; c0 < N; c0 += kWave) {
+        const uint32_t g = base + c0 + lane;
+        if (in(g)) { ksum += key(g); ++kn; }
+    }
+    // each slot is classified by the same lane in both passes, so a lane's
+    // own rounding of the mean cannot drop or repeat a slot
+    const float thr = wave_sum_f(ksum) / fmaxf((float)wave_sum_i(kn), 1.f);
+    int n = 0;
+#pragma unroll
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int c0 = 0; c0 < N; c0 += kWave) {
+            const int li = c0 + lane;
+            const uint32_t g = base + li;
+            bool sel = in(g);
+            if (sel) {
+                const bool longq = key(g) >= thr;
+                sel = pass == 0 ? longq : !longq;
+            }
+            const uint64_t m = __ballot(sel);
+            if (sel) L[n + (int)lane_prefix(m)] = li;
+            n += __popcll(m);
+        }
+    }
+    return n;
+}
+
 template <int D, bool GUIDED, bool STATS>
 __device__ __forceinline__ void walk_body(const WalkParams& P)
 {
@@ -452,47 +489,18 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                 });
         }
         wave_sync();
-        // the walks that step on, in two groups: first those whose star
-        // queries are likely long (far from the Dirichlet boundary, or on
-        // the Neumann boundary, where normal cones prune little), then the
-        // rest; each group in slot order.  A phase hands out its list in
-        // order, so long queries start early instead of trailing at the end
-        // of the phase while the other lanes idle, and neighbouring lanes
-        // read neighbouring slots.
-        {
-            float ksum = 0.f;
-            int kn = 0;
-            for (int c0 = 0; c0 < N; c0 += kWave) {
-                const uint32_t g = base + c0 + lane;
-                if (pv.i(F::STAT, g) == ST_STEP) {
-                    ksum += pv.f(F::DD, g) * (pv.i(F::ONP, g) >= 0 ? 4.f : 1.f);
-                    ++kn;
-                }
-            }
-            const float thr = wave_sum_f(ksum) / fmaxf((float)wave_sum_i(kn), 1.f);
-#pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int c0 = 0; c0 < N; c0 += kWave) {
-                    const int li = c0 + lane;
-                    const uint32_t g = base + li;
-                    bool stp = pv.i(F::STAT, g) == ST_STEP;
-                    if (stp) {
-                        const bool longq = pv.f(F::DD, g) * (pv.i(F::ONP, g) >= 0 ? 4.f : 1.f) >= thr;
-                        stp = pass == 0 ? longq : !longq;
-                    }
-                    const uint64_t m = __ballot(stp);
-                    if (stp) L_step[n_step + (int)lane_prefix(m)] = li;
-                    n_step += __popcll(m);
-                }
-            }
-        }
+        // the walks that step on; the closest-silhouette search runs long
+        // far from the Dirichlet boundary and on the Neumann boundary, where
+        // normal cones prune little
+        n_step = list_long_first(L_step, N, base, lane, [&](uint32_t g) { return pv.i(F::STAT, g) == ST_STEP; },
+                                 [&](uint32_t g) { return pv.f(F::DD, g) * (pv.i(F::ONP, g) >= 0 ? 4.f : 1.f); });
         wave_sync();
         if (n_step == 0) continue;
 
         // ---- closest silhouette -> star radius; uniform direction
         {
             float x[D], dD = 0.f;
-            int onp = -1;
+            int onp = -1, piece = -1;
             Trav q;
             run_phase(L_step, n_step, (int32_t*)nullptr, dummy_n, lane, batch, witer[1],
                 [&](int slot) {
@@ -501,9 +509,10 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                     for (int i = 0; i < D; ++i) x[i] = pv.f(F::X + i, g);
                     onp = pv.i(F::ONP, g);
                     dD = pv.f(F::DD, g);
+                    piece = onp >= 0 && G.sil.piece ? G.sil.piece[onp] : -1;
                     trav_begin(G.sil, dD * dD, q);
                 },
-                [&]() { return closest_silhouette_step<D>(G.sil, x, onp, q, st, &sq[1]); },
+                [&]() { return closest_silhouette_step<D>(G.sil, x, onp, piece, q, st, &sq[1]); },
                 [&](int slot) {
                     const uint32_t g = base + slot;
                     const float r = fmaxf(fminf(dD, sqrtf(q.best)), P.r_min);
@@ -618,7 +627,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                     });
             }
             wave_sync();
-            // visibility candidates in slot order (see the stepping list)
+            // visibility candidates in slot order
             for (int c0 = 0; c0 < N; c0 += kWave) {
                 const int li = c0 + lane;
                 const bool vis = pv.i(F::STAT, base + li) == ST_VIS;
@@ -876,7 +885,8 @@ __global__ __launch_bounds__(256) void reduce_points(const float* __restrict__ s
 }
 
 template <int D>
-__global__ __launch_bounds__(64) void query_kernel(const DevGeom G, const float* pts, int64_t n, float* d_dir,
+__global__ __launch_bounds__(64) void query_kernel(const DevGeom G, const float* pts, int64_t n, const int32_t* on_prim,
+                                                   float* d_dir,
                                                    float* xbar, float* d_sil, const float* ray_dir,
                                                    const float* ray_tmax, float* ray_t, int32_t* ray_prim)
 {
@@ -898,7 +908,12 @@ __global__ __launch_bounds__(64) void query_kernel(const DevGeom G, const float*
             for (int c = 0; c < D; ++c) xbar[i * D + c] = pr >= 0 ? xb[c] : INFINITY;
         }
     }
-    if (d_sil) d_sil[i] = sqrtf(closest_silhouette<D>(G.sil, x, INFINITY, -1, st));
+    if (d_sil) {
+        // a point on a Neumann primitive sees that primitive from the front
+        const int32_t q = on_prim ? on_prim[i] : -1;
+        const int onp = q >= 0 && q < G.n_caller && G.neu_id ? G.neu_id[q] : -1;
+        d_sil[i] = sqrtf(closest_silhouette<D>(G.sil, x, INFINITY, onp, st));
+    }
     if (ray_dir && ray_t) {
         float nu[D];
 #pragma unroll
@@ -1149,8 +1164,9 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     return WOST_OK;
 }
 
-extern "C" int wost_query(const wost_geom* geom, const float* pts, int64_t n, float* d_dir, float* xbar, float* d_sil,
-                          const float* ray_dir, const float* ray_tmax, float* ray_t, int32_t* ray_prim, void* stream)
+extern "C" int wost_query(const wost_geom* geom, const float* pts, int64_t n, const int32_t* on_prim, float* d_dir,
+                          float* xbar, float* d_sil, const float* ray_dir, const float* ray_tmax, float* ray_t,
+                          int32_t* ray_prim, void* stream)
 {
     if (!geom) { set_error("wost_query: NULL geometry"); return WOST_EINVAL; }
     if (!geom->dev) { set_error("wost_query: geometry not uploaded"); return WOST_ESTATE; }
@@ -1165,9 +1181,11 @@ extern "C" int wost_query(const wost_geom* geom, const float* pts, int64_t n, fl
     hipStream_t s = (hipStream_t)stream;
     const int grid = (int)((n + 63) / 64);
     if (geom->dim == 2)
-        hipLaunchKernelGGL(query_kernel<2>, dim3(grid), dim3(64), 0, s, G, pts, n, d_dir, xbar, d_sil, ray_dir, ray_tmax, ray_t, ray_prim);
+        hipLaunchKernelGGL(query_kernel<2>, dim3(grid), dim3(64), 0, s, G, pts, n, on_prim, d_dir, xbar, d_sil, ray_dir,
+                           ray_tmax, ray_t, ray_prim);
     else
-        hipLaunchKernelGGL(query_kernel<3>, dim3(grid), dim3(64), 0, s, G, pts, n, d_dir, xbar, d_sil, ray_dir, ray_tmax, ray_t, ray_prim);
+        hipLaunchKernelGGL(query_kernel<3>, dim3(grid), dim3(64), 0, s, G, pts, n, on_prim, d_dir, xbar, d_sil, ray_dir,
+                           ray_tmax, ray_t, ray_prim);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("wost_query: launch failed: %s", hipGetErrorString(e)); return WOST_EHIP; }
     return WOST_OK;

@@ -24,8 +24,10 @@ constexpr int kWave = 64;
 //   2D + 1 ...   per-hierarchy child data:
 //                  Dirichlet     none                          stride 2D + 1
 //                  Neumann       subtree measure (1 float4)    stride 2D + 2
-//                  silhouettes   normal cone axis x, y (, z)
-//                                and cos of its half-angle     stride 3D + 2
+//                  silhouettes   normal cone axis x, y (, z), cos
+//                                of its half-angle, and the convex
+//                                piece all its candidates are interior
+//                                to (int bits, -1 for none)    stride 3D + 3
 constexpr int32_t kEmptyRef = (int32_t)0x80000000;
 constexpr int kLeafMax = 64;
 constexpr int64_t kMaxLeafFirst = (1ll << 25) - kLeafMax;   // first < this
@@ -35,7 +37,8 @@ template <int D> struct Layout4 {
     static constexpr int kAux = 2 * D + 1;
     static constexpr int kDirStride = 2 * D + 1;
     static constexpr int kNeuStride = 2 * D + 2;
-    static constexpr int kSilStride = 3 * D + 2;
+    static constexpr int kSilStride = 3 * D + 3;
+    static constexpr int kPiece = 3 * D + 2;
 };
 
 __host__ __device__ inline int32_t leaf_ref(int32_t first, int32_t count) { return -1 - (first * kLeafMax + count - 1); }
@@ -56,6 +59,8 @@ struct DevBvh {
     const float4* prims;    // prim records
     const float4* pextra;   // Neumann per-primitive normal + measure (or null)
     const int32_t* orig;    // internal primitive id -> caller primitive index
+    const int32_t* piece;   // silhouettes: convex piece of each Neumann primitive
+                            // (internal Neumann id), -1 for none; else null
     int32_t n_nodes;
     int32_t n_prims;
 };
@@ -67,6 +72,8 @@ struct DevGeom {
     int32_t dim;
     float diag;             // AABB diagonal L
     float tau;              // facing / self-intersection tolerance (1e-6 L)
+    const int32_t* neu_id;  // caller primitive index -> internal Neumann id (-1: Dirichlet)
+    int64_t n_caller;       // caller primitives
     float lo[3], hi[3];
 };
 
@@ -89,7 +96,9 @@ struct wost_geom {
     // host image of the device buffer and section offsets (bytes)
     uint8_t* image = nullptr;
     int64_t bytes = 0;
-    struct Sec { int64_t nodes, prims, pextra, orig; int32_t n_nodes, n_prims; } sec[3];
+    struct Sec { int64_t nodes, prims, pextra, orig, piece; int32_t n_nodes, n_prims; } sec[3];
+    int64_t off_neu_id = -1;        // caller id -> internal Neumann id table
+    int64_t n_caller = 0;
     void* dev = nullptr;    // caller buffer after upload
     int32_t* orig_host = nullptr;    // concatenated: dir, neu prims -> caller ids
     wost::DevGeom devgeom() const;

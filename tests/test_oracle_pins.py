@@ -112,6 +112,33 @@ def test_silhouette_convex_polygon_is_empty(oracle_lib):
     assert np.all(np.isinf(dS))
 
 
+def test_silhouette_from_the_boundary_of_a_convex_polygon(oracle_lib):
+    """Seen from a point on a convex polygon's boundary no vertex is a
+    silhouette.  Points rounded off their edge by ~1e-8 would see their own
+    edge from behind, so the edge each point lies on is passed as its own
+    primitive, which faces it from the front (a walker standing on it)."""
+    s = _regular_polygon_scene(bc_value=1)
+    o = oracle_lib.OracleScene(s)
+    rng = np.random.default_rng(5)
+    q = rng.integers(0, len(s.prims), 2000)
+    a, b = s.verts[s.prims[q, 0]], s.verts[s.prims[q, 1]]
+    t = rng.uniform(0.05, 0.95, (2000, 1))
+    x = np.asarray(a + t * (b - a), np.float32).astype(np.float64)
+    assert np.all(np.isinf(o.silhouette(x, on_prim=q)))
+    # without it, the points that lie outside their edge's line see its two
+    # ends as silhouettes (the rounding is what decides)
+    # (facing tolerance 1e-12 of the AABB diagonal 2 sqrt 2, inward normal =
+    # left normal of the counter-clockwise edges)
+    e = b - a
+    nin = np.stack([-e[:, 1], e[:, 0]], 1) / np.linalg.norm(e, axis=1, keepdims=True)
+    sd = np.einsum("ij,ij->i", x - a, nin)
+    tau = 1e-12 * 2.0 * math.sqrt(2.0)
+    plain = o.silhouette(x)
+    clear = np.abs(sd + tau) > 1e-15
+    assert (sd < -tau).any()
+    np.testing.assert_array_equal(np.isfinite(plain)[clear], (sd < -tau)[clear])
+
+
 def test_star_radius_gives_star_shaped_region(oracle_lib):
     """Within r = min(d_D, d_S) every ray from x crosses the Neumann boundary
     at most once (the star region is star-shaped as seen from x)."""
