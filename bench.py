@@ -53,7 +53,7 @@ def bytes_per_step(cost, dim):
 
 
 WALK_SOURCES = ["walk.hip", "geom_device.h", "guide_device.h", "walk_common.h", "wost_internal.h", "../build.py"]
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_kernel2_c3_guided_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_kernel2g_c3_guided_traffic.md")
 
 
 def walk_sources_sha256():
@@ -230,7 +230,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(tr["hbm_bytes_per_launch"]) if tr else None,
-                "kernel": "wost::walk_kernel2<true, false> (guided 2D walk)",
+                "kernel": "wost::walk_kernel2g<false> (guided 2D walk)",
                 "bytes_per_step": round(bps_g, 1), "uniform_bytes_per_step": round(bps_u, 1),
                 "walk_s": round(walk_s, 4), "steps": total_steps,
                 "launches": n_launch, "avg_launch_ms": round(walk_s / max(n_launch, 1) * 1e3, 3),
