@@ -105,6 +105,61 @@ def cpu_baseline(scene, max_seconds=20.0):
                       % (len(pts), wpp, steps, dt)}
 
 
+def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2):
+    """Sampling-mode ablations (number of lobes K, the selection probability
+    c: 0 = uniform, 0.5 fixed, 1 = guided only, learned) and the
+    training-schedule sweep (how many walks per point train the guide, Adam
+    steps per batch), each a full solve of the bench workload; mean of `reps`
+    seeds.  Prints one JSON line per configuration."""
+    import torch
+
+    def one(label, sampling="mis_learned", K=8, reflect=True, c_fixed=0.5, until=args.train_until, steps=16):
+        rows = []
+        for r in range(reps):
+            seed = 500 + r
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            if sampling == "uniform":
+                pb = W.Problem.from_scene(s)
+                e0.record()
+                acc = W.solve(geom, pb, pts, args.wpp, seed=18944 + seed)
+                e1.record()
+                torch.cuda.synchronize()
+                ph = {"walk": e0.elapsed_time(e1) * 1e-3, "train": 0.0, "tail": 0.0}
+            else:
+                pb = W.Problem.from_scene(s, sampling=sampling, reflect=reflect, c_fixed=c_fixed)
+                g = W.Guide(W.GuideConfig.for_scene(s, K=K), seed=seed)
+                sched = OnlineSchedule(batch_wpp=args.batch_wpp, train_until_wpp=until, max_steps_per_batch=steps)
+                e0.record()
+                acc, info = online_solve(geom, pb, pts, args.wpp, g, sched, seed=18944 + seed)
+                e1.record()
+                torch.cuda.synchronize()
+                ph = info["phase_s"]
+            t = e0.elapsed_time(e1) * 1e-3
+            m = acc.estimates()[0].cpu().numpy()
+            st = acc.stats()
+            mse = float(np.mean((m - u) ** 2))
+            rows.append(dict(time_s=t, rel_mse=rel_mse(m, u), mse=mse, mse_x_time=mse * t,
+                             steps_per_walk=st["steps"] / max(st["walks"], 1), walk_s=ph["walk"],
+                             train_s=ph["train"], tail_s=ph["tail"]))
+        out = {k: float(np.mean([r[k] for r in rows])) for k in rows[0]}
+        out.update(label=label, sampling=sampling, K=K, reflect=reflect, c_fixed=c_fixed if sampling == "mis_fixed"
+                   else None, train_until_wpp=until if sampling != "uniform" else 0,
+                   adam_steps_per_batch=steps if sampling != "uniform" else 0, reps=reps)
+        print(json.dumps(out), flush=True)
+
+    one("uniform (c = 0)", sampling="uniform")
+    one("MIS, c = 0.5 fixed", sampling="mis_fixed", c_fixed=0.5)
+    one("guided only (c = 1)", sampling="guided_only")
+    one("MIS, learned c (default)")
+    for K in (4, 16):
+        one("learned c, K = %d" % K, K=K)
+    for until in (128, 256):
+        one("train until %d wpp" % until, until=until)
+    for steps in (8, 32):
+        one("%d Adam steps per batch" % steps, steps=steps)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +172,9 @@ def main():
     ap.add_argument("--print-walk-sha", action="store_true", help="print the walk kernel source hash and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--ablations", action="store_true",
+                    help="instead of the bench line: sampling-mode ablations (K, selection c) and the "
+                         "training-schedule sweep on the same workload, one JSON line per configuration")
     args = ap.parse_args()
     if args.print_walk_sha:
         print(walk_sources_sha256())
@@ -167,6 +225,9 @@ def main():
         guided_step(100 + w)
         uniform_step(100 + w)
     torch.cuda.synchronize()
+    if args.ablations:
+        run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args)
+        return
 
     # ---- timed region: K guided solves
     t0 = time.perf_counter()

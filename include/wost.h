@@ -150,7 +150,9 @@ typedef struct {
     float rr_q;             /* roulette survival probability                             */
     int32_t sampling;       /* WOST_SAMPLING_*                                           */
     float c_fixed;          /* selection probability for WOST_SAMPLING_MIS_FIXED         */
-    int32_t reflect;        /* 1: reflect invalid draws at Neumann points (Sec. 4.3)     */
+    int32_t reflect;        /* must be 1 for guided sampling: draws into the wall at a
+                               Neumann point are reflected (Sec. 4.3); uniform
+                               draws there always use the valid half             */
 } wost_problem;
 
 /* Training records written by guided walks (one per drawn direction), in a

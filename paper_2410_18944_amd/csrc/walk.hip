@@ -1096,6 +1096,12 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     P.slot_steps = walk_steps;
     P.counters = (unsigned long long*)dev_counters;
     P.cost = g_cost;
+    if (guided && !pb->reflect) {
+        // guided draws into the wall are always reflected (Sec. 4.3); the
+        // variant that wastes them is not implemented
+        set_error("wost_solve: guided sampling needs reflect = 1");
+        return WOST_EUNSUPPORTED;
+    }
     if (guided) {
         int rc = guide_prepare(guide, dim, P.guide);
         if (rc != WOST_OK) return rc;

@@ -81,11 +81,11 @@ def _scene_3d():
 
 # ----------------------------------------------------------------------------- inference
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_guide_infer_matches_fp64_reference(W, dim):
+@pytest.mark.parametrize("dim,K", [(2, 8), (3, 8), (2, 4), (2, 16)])
+def test_guide_infer_matches_fp64_reference(W, dim, K):
     from oracle import guide_ref as G
     s = _scene_2d() if dim == 2 else _scene_3d()
-    kw = {} if dim == 2 else dict(log2_table=14)
+    kw = dict(K=K) if dim == 2 else dict(log2_table=14, K=K)
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=dim, **kw)
     rng = np.random.default_rng(7)
     lo, hi = rcfg.lo, rcfg.hi
@@ -115,12 +115,12 @@ def _philox_blocks(O, n, j, step, blocks, seed):
     return (w >> 8).astype(np.float64) * 2.0 ** -24
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-@pytest.mark.parametrize("mode", ["mis_learned", "mis_fixed", "guided_only"])
-def test_guide_sample_matches_reference_on_same_words(W, O, dim, mode):
+@pytest.mark.parametrize("dim,mode,K", [(d, m, 8) for d in (2, 3) for m in ("mis_learned", "mis_fixed", "guided_only")]
+                         + [(2, "mis_learned", 4), (2, "mis_learned", 16)])
+def test_guide_sample_matches_reference_on_same_words(W, O, dim, mode, K):
     from oracle import guide_ref as G
     s = _scene_2d() if dim == 2 else _scene_3d()
-    kw = {} if dim == 2 else dict(log2_table=14)
+    kw = dict(K=K) if dim == 2 else dict(log2_table=14, K=K)
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=10 + dim, **kw)
     rng = np.random.default_rng(8 + dim)
     n = 2048
@@ -208,6 +208,8 @@ def test_guided_c2_unbiased_with_reflection(W):
     geom = W.Geometry.from_scene(s)
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=41)
     say("guided C2", len(pts))
+    with pytest.raises(RuntimeError, match="reflect"):
+        _solve(W, s, geom, W.Problem.from_scene(s, sampling="mis_learned", reflect=False), pts[:8], 4, guide=g)
     r = _solve(W, s, geom, W.Problem.from_scene(s, sampling="mis_learned"), pts, 512, guide=g)
     zscore_check(r["mean"], r["se"], exact_solution(s, pts), r["n"], label="guided C2")
     u = _solve(W, s, geom, W.Problem.from_scene(s), pts, 512)
@@ -294,11 +296,11 @@ def _synthetic_records(W, rcfg, n, rng, dim):
     return rec, (f64(x), f64(nu), f64(nr), on, f64(ps), f64(pt))
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_loss_and_backward_match_fp64_reference(W, dim):
+@pytest.mark.parametrize("dim,K", [(2, 8), (3, 8), (2, 4), (2, 16)])
+def test_loss_and_backward_match_fp64_reference(W, dim, K):
     from oracle import guide_ref as G
     s = _scene_2d() if dim == 2 else _scene_3d()
-    kw = {} if dim == 2 else dict(log2_table=14)
+    kw = dict(K=K) if dim == 2 else dict(log2_table=14, K=K)
     # MLP weights at 0.6x He scale keep kappa' in the range a trained guide uses
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=70 + dim, mlp_gain=0.6, **kw)
     rng = np.random.default_rng(71 + dim)
