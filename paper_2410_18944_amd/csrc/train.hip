@@ -40,7 +40,9 @@ struct TrainArgs {
     float* loss_sum;        // device scalar += loss_scale * sum(loss) (or null)
     float loss_scale;
     float* grad;            // gradient vector (grid part first)
-    float* partials;        // [gridDim.x][p_mlp]
+    float* partials;        // [gridDim.x][n_frag] weight gradients in MFMA fragment order
+    int32_t n_frag;         // floats per workgroup row (= 256 x weight-gradient blocks)
+    int32_t blk_off[kMaxLayers];   // first 16x16 block of each layer in a row
     float* gco;             // coarse-level feature gradients [2 n_coarse][count]
     int32_t n_coarse;       // levels below this are staged in gco, not scattered
     int32_t backward;
@@ -218,16 +220,19 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
     const int kb0 = g.kb[0];
     const int rows_act = 16 * kb0 + 64 * (L - 1);
     const int rmax = out_pad > 64 ? out_pad : 64;
-    float* s_dw = smem;
-    float* s_y = smem + (a.backward ? a.p_mlp : 0);
-    _Float16* s_act = (_Float16*)(s_y + 64 * ystride);
-    _Float16* s_d0 = s_act + rows_act * 64;
-    _Float16* s_d1 = s_d0 + rmax * 64;
+    // LDS: the raw outputs s_y share their space with one of the two dZ
+    // buffers (s_y is dead once the output gradient has been staged in s_d1)
+    const int ybytes = 64 * ystride * 4, dbytes = rmax * 64 * 2;
+    float* s_y = smem;
+    _Float16* s_d0 = (_Float16*)smem;
+    _Float16* s_act = (_Float16*)((char*)smem + (ybytes > dbytes ? ybytes : dbytes));
+    _Float16* s_d1 = s_act + rows_act * 64;
     const int64_t T = 1ll << g.log2T;
-
+    // this workgroup's weight-gradient row, accumulated across its tiles in
+    // the MFMA fragment layout (each lane owns a float4 of every block)
+    float4* const prow = a.backward ? (float4*)(a.partials + (int64_t)blockIdx.x * a.n_frag) : nullptr;
     if (a.backward)
-        for (int j = lane; j < a.p_mlp; j += 64) s_dw[j] = 0.f;
-    __syncthreads();
+        for (int j = lane; j < a.n_frag / 4; j += 64) prow[j] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     const int64_t n_tiles = (a.count + 63) / 64;
     float loss_acc = 0.f;
@@ -320,16 +325,15 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
         float mx = 0.f;
         for (int j = 0; j < out_pad; ++j) mx = fmaxf(mx, fabsf(yrow[j]));
         float Sc = pow2_scale(wave_max(mx));
-        for (int j = 0; j < out_pad; ++j) s_d0[j * 64 + lane] = (_Float16)(yrow[j] * Sc);
+        for (int j = 0; j < out_pad; ++j) s_d1[j * 64 + lane] = (_Float16)(yrow[j] * Sc);
         __syncthreads();
         // ---------------- backward
-        _Float16* cur = s_d0;
-        _Float16* nxt = s_d1;
+        _Float16* cur = s_d1;
+        _Float16* nxt = s_d0;
         for (int layer = L - 1; layer >= 0; --layer) {
             const int rows_out = layer == L - 1 ? out_pad : 64;
             const int rows_in = layer == 0 ? 16 * kb0 : 64;
             const _Float16* act = s_act + (layer == 0 ? 0 : (16 * kb0 + 64 * (layer - 1))) * 64;
-            const int outr = a.out[layer];
             const float inv_sc = 1.f / Sc;
             // weight gradient: dW^T[out][in] += sum_walk dZ^T[out][walk] H[walk][in]
             for (int mb = 0; mb < rows_out / 16; ++mb) {
@@ -341,12 +345,13 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
                         const half4_t Bv = lds_h4(act + (16 * nb + col) * 64 + 16 * kk + 4 * g4);
                         c = __builtin_amdgcn_mfma_f32_16x16x16f16(Av, Bv, c, 0, 0, 0);
                     }
-                    const int in_i = 16 * nb + col;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int o = 16 * mb + 4 * g4 + e;
-                        if (o < outr) s_dw[a.off[layer] + in_i * outr + o] += c[e] * inv_sc;
-                    }
+                    float4* const dst = prow + (a.blk_off[layer] + mb * (rows_in / 16) + nb) * 64 + lane;
+                    float4 v = *dst;
+                    v.x = fmaf(c[0], inv_sc, v.x);
+                    v.y = fmaf(c[1], inv_sc, v.y);
+                    v.z = fmaf(c[2], inv_sc, v.z);
+                    v.w = fmaf(c[3], inv_sc, v.w);
+                    *dst = v;
                 }
             }
             // data gradient dH^T = W dZ^T (rows = input features of this layer)
@@ -473,11 +478,6 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
         const float s = wave_sum(loss_acc);
         if (lane == 0) atomicAdd(a.loss_sum, s * a.loss_scale);
     }
-    if (a.backward) {
-        __syncthreads();
-        float* dst = a.partials + (int64_t)blockIdx.x * a.p_mlp;
-        for (int j = lane; j < a.p_mlp; j += 64) dst[j] = s_dw[j];
-    }
 }
 
 // grad[mlp] += sum over workgroup partials, fixed order (deterministic)
@@ -556,12 +556,29 @@ __global__ __launch_bounds__(512) void coarse_scatter_kernel(const GuideDev g, c
     }
 }
 
-__global__ void reduce_partials(const float* partials, int nblk, int p_mlp, float* grad_mlp)
+struct FragMap {
+    int32_t n_layers;
+    int32_t off[kMaxLayers], in[kMaxLayers], out[kMaxLayers], blk_off[kMaxLayers], nb[kMaxLayers];
+};
+
+// Sums the workgroups' weight-gradient rows into the MLP gradient.  Weight
+// (layer l, input i, output o) sits at l's offset + i * out + o; in a row it
+// is element 4 * lane + e of block blk_off[l] + (o / 16) * nb[l] + i / 16,
+// with lane = 16 ((o / 4) % 4) + i % 16 and e = o % 4 (the 16x16x16 MFMA
+// accumulator layout).
+__global__ void reduce_partials(const float* partials, int nblk, int n_frag, int p_mlp, FragMap m, float* grad_mlp)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= p_mlp) return;
+    int l = 0;
+    while (l + 1 < m.n_layers && j >= m.off[l + 1]) ++l;
+    const int r = j - m.off[l];
+    const int i = r / m.out[l], o = r - i * m.out[l];
+    const int lane = 16 * ((o >> 2) & 3) + (i & 15);
+    const int blk = m.blk_off[l] + (o >> 4) * m.nb[l] + (i >> 4);
+    const int f = blk * 256 + lane * 4 + (o & 3);
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += partials[(int64_t)b * p_mlp + j];
+    for (int b = 0; b < nblk; ++b) s += partials[(int64_t)b * n_frag + f];
     grad_mlp[j] += s;
 }
 
@@ -612,7 +629,7 @@ static int train_grid_cap()
         else
             g_train_cu = 256;
     }
-    return 2 * g_train_cu;
+    return 4 * g_train_cu;
 }
 
 // LDS budget of the coarse-level scatter: the longest prefix of dense levels
@@ -650,25 +667,37 @@ static int coarse_scatter_grid(int64_t count)
     // about 2048 records per workgroup, at most half a workgroup per CU: the
     // flush adds (grid x staged entries) global atomics
     const int64_t want = (count + 2047) / 2048;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::max(1, train_grid_cap() / 4)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::max(1, train_grid_cap() / 8)));
+}
+
+// floats per workgroup row of weight-gradient partials: one 16x16 block per
+// (16 outputs, 16 inputs) of every layer, output rows padded to 16
+static int64_t frag_floats(const GuideDev& g)
+{
+    int64_t blocks = 0;
+    for (int l = 0; l < g.n_layers; ++l) {
+        const int rows_out = l == g.n_layers - 1 ? g.out_pad : 64;
+        const int rows_in = l == 0 ? 16 * g.kb[0] : 64;
+        blocks += (rows_out / 16) * (rows_in / 16);
+    }
+    return blocks * 256;
 }
 
 static int64_t train_ws_partials(const wost_guide* gd, int64_t count)
 {
     const int64_t n_tiles = (count + 63) / 64;
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_tiles, train_grid_cap()));
-    return (grid * (gd->n_params - gd->n_grid) * 4 + 255) / 256 * 256;
+    return (grid * frag_floats(gd->dev) * 4 + 255) / 256 * 256;
 }
 
 static size_t train_lds_bytes(const wost_guide* gd, bool backward)
 {
+    (void)backward;
     const GuideDev& g = gd->dev;
     const int rows_act = 16 * g.kb[0] + 64 * (g.n_layers - 1);
     const int rmax = g.out_pad > 64 ? g.out_pad : 64;
-    const int64_t p_mlp = gd->n_params - gd->n_grid;
-    size_t b = sizeof(float) * 64 * (g.out_pad + 1) + 2 * (size_t)rows_act * 64 + 2 * 2 * (size_t)rmax * 64;
-    if (backward) b += sizeof(float) * p_mlp;
-    return b;
+    const size_t ybytes = sizeof(float) * 64 * (g.out_pad + 1), dbytes = 2 * (size_t)rmax * 64;
+    return (ybytes > dbytes ? ybytes : dbytes) + 2 * (size_t)rows_act * 64 + dbytes;
 }
 
 static int launch_train(const wost_guide* gd, const wost_records* rec, int64_t begin, int64_t count, float e_mis,
@@ -698,11 +727,25 @@ static int launch_train(const wost_guide* gd, const wost_records* rec, int64_t b
     a.grad = grad;
     a.backward = backward ? 1 : 0;
     a.p_mlp = (int32_t)(gd->n_params - gd->n_grid);
+    FragMap fm;
+    memset(&fm, 0, sizeof(fm));
+    fm.n_layers = g.n_layers;
+    int blk = 0;
     for (int l = 0; l < g.n_layers; ++l) {
         a.off[l] = (int32_t)(gd->layer_off[l] - gd->n_grid);
         a.in[l] = gd->layer_in[l];
         a.out[l] = gd->layer_out[l];
+        const int rows_out = l == g.n_layers - 1 ? g.out_pad : 64;
+        const int rows_in = l == 0 ? 16 * g.kb[0] : 64;
+        a.blk_off[l] = blk;
+        fm.off[l] = a.off[l];
+        fm.in[l] = a.in[l];
+        fm.out[l] = a.out[l];
+        fm.blk_off[l] = blk;
+        fm.nb[l] = rows_in / 16;
+        blk += (rows_out / 16) * (rows_in / 16);
     }
+    a.n_frag = blk * 256;
     const int64_t n_tiles = (count + 63) / 64;
     const int grid = (int)std::min<int64_t>(n_tiles, train_grid_cap());
     if (backward) {
@@ -720,7 +763,7 @@ static int launch_train(const wost_guide* gd, const wost_records* rec, int64_t b
     else hipLaunchKernelGGL(train_kernel<3>, dim3(grid), dim3(64), lds, s, g, a);
     if (backward) {
         hipLaunchKernelGGL(reduce_partials, dim3((a.p_mlp + 255) / 256), dim3(256), 0, s, (const float*)a.partials, grid,
-                           a.p_mlp, grad + gd->n_grid);
+                           a.n_frag, a.p_mlp, fm, grad + gd->n_grid);
         if (a.n_coarse) {
             const size_t cl = sizeof(float) * (size_t)coarse_lds_floats(g, a.n_coarse);
             const int cg = coarse_scatter_grid(count);
