@@ -373,6 +373,21 @@ __device__ __forceinline__ uint32_t leaf_mask(const int4& ref, F pass)
     return m;
 }
 
+// Takes the leaf child with the smallest key out of the mask lm.  Leaves are
+// tested nearest first, so the first one usually sets the bound that lets the
+// others go untested.
+__device__ __forceinline__ int pop_nearest(uint32_t& lm, const float* key)
+{
+    int kb = 0;
+    float kv = INFINITY;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (((lm >> k) & 1u) && (!any || key[k] < kv)) { kb = k; kv = key[k]; any = true; }
+    lm &= ~(1u << kb);
+    return kb;
+}
+
 // ---- closest Dirichlet point: q.best = squared distance, q.prim = primitive
 template <int D, class S>
 __device__ __forceinline__ bool closest_dirichlet_step(const DevBvh& b, const float* x, Trav& q, const LdsStack& st,
@@ -387,8 +402,8 @@ __device__ __forceinline__ bool closest_dirichlet_step(const DevBvh& b, const fl
     for (int k = 0; k < 4; ++k) key[k] = box_dist2<D>(n.box(k), x);   // empty children: +inf
     uint32_t lm = leaf_mask(n.ref, [&](int k) { return key[k] < q.best; });
     while (lm) {
-        const int k = __builtin_ctz(lm);
-        lm &= lm - 1;
+        const int k = pop_nearest(lm, key);
+        if (!(key[k] < q.best)) break;
         const int r = comp(n.ref, k);
         const int f = leaf_first(r), c = leaf_count(r);
         for (int j = f; j < f + c; ++j) {
@@ -526,8 +541,8 @@ __device__ __forceinline__ bool closest_silhouette_step(const DevBvh& b, const f
     }
     uint32_t lm = leaf_mask(n.ref, [&](int k) { return key[k] < q.best; });
     while (lm) {
-        const int k = __builtin_ctz(lm);
-        lm &= lm - 1;
+        const int k = pop_nearest(lm, key);
+        if (!(key[k] < q.best)) break;
         const int r = comp(n.ref, k);
         const int f = leaf_first(r), c = leaf_count(r);
         for (int j = f; j < f + c; ++j) q.best = fminf(q.best, sil_prim_dist2<D>(b.prims, j, x, onp)), stat_prim(s);
@@ -607,8 +622,10 @@ __device__ __forceinline__ bool ray_neumann_step(const DevBvh& b, const float* x
         key[k] = comp(n.ref, k) != kEmptyRef ? ray_box<D>(n.box(k), x, q.inv, -back, q.t.best) : INFINITY;
     uint32_t lm = leaf_mask(n.ref, [&](int k) { return key[k] < INFINITY; });
     while (lm) {
-        const int k = __builtin_ctz(lm);
-        lm &= lm - 1;
+        // nearest entry first; a leaf entered beyond the best hit holds no
+        // nearer one (the slab slack keeps every crossing inside its box)
+        const int k = pop_nearest(lm, key);
+        if (!(key[k] <= q.t.best)) break;
         const int r = comp(n.ref, k);
         const int f = leaf_first(r), c = leaf_count(r);
         for (int j = f; j < f + c; ++j) {
