@@ -565,21 +565,39 @@ struct FragMap {
 // (layer l, input i, output o) sits at l's offset + i * out + o; in a row it
 // is element 4 * lane + e of block blk_off[l] + (o / 16) * nb[l] + i / 16,
 // with lane = 16 ((o / 4) % 4) + i % 16 and e = o % 4 (the 16x16x16 MFMA
-// accumulator layout).
-__global__ void reduce_partials(const float* partials, int nblk, int n_frag, int p_mlp, FragMap m, float* grad_mlp)
+// accumulator layout).  Thread t of block (x, y) sums float4 t of rows y,
+// y + gridDim.y, ... (coalesced), then adds each of its four sums to its
+// weight (padding outputs o >= out are dropped).
+__global__ __launch_bounds__(256) void reduce_partials(const float* partials, int nrows, int n_frag, FragMap m,
+                                                       float* grad_mlp)
 {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= p_mlp) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;     // float4 index in a row
+    if (4 * t >= n_frag) return;
+    const float4* p = (const float4*)partials;
+    const int n4 = n_frag / 4;
+    float4 s0 = make_float4(0.f, 0.f, 0.f, 0.f), s1 = s0;
+    int r = blockIdx.y;
+    for (; r + (int)gridDim.y < nrows; r += 2 * gridDim.y) {
+        const float4 a = p[(int64_t)r * n4 + t], b = p[(int64_t)(r + gridDim.y) * n4 + t];
+        s0.x += a.x; s0.y += a.y; s0.z += a.z; s0.w += a.w;
+        s1.x += b.x; s1.y += b.y; s1.z += b.z; s1.w += b.w;
+    }
+    if (r < nrows) {
+        const float4 a = p[(int64_t)r * n4 + t];
+        s0.x += a.x; s0.y += a.y; s0.z += a.z; s0.w += a.w;
+    }
+    const float sum[4] = {s0.x + s1.x, s0.y + s1.y, s0.z + s1.z, s0.w + s1.w};
+    const int blk = t / 64, lane = t % 64;
     int l = 0;
-    while (l + 1 < m.n_layers && j >= m.off[l + 1]) ++l;
-    const int r = j - m.off[l];
-    const int i = r / m.out[l], o = r - i * m.out[l];
-    const int lane = 16 * ((o >> 2) & 3) + (i & 15);
-    const int blk = m.blk_off[l] + (o >> 4) * m.nb[l] + (i >> 4);
-    const int f = blk * 256 + lane * 4 + (o & 3);
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += partials[(int64_t)b * n_frag + f];
-    grad_mlp[j] += s;
+    while (l + 1 < m.n_layers && blk >= m.blk_off[l + 1]) ++l;
+    const int lb = blk - m.blk_off[l];
+    const int mb = lb / m.nb[l], nb = lb % m.nb[l];
+    const int i = 16 * nb + (lane & 15);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int o = 16 * mb + 4 * (lane >> 4) + e;
+        if (o < m.out[l] && i < m.in[l]) atomicAdd(grad_mlp + m.off[l] + i * m.out[l] + o, sum[e]);
+    }
 }
 
 __global__ void adam_kernel(float* p, float* m, float* v, float* gr, int64_t n, float lr_t, float b1, float b2,
@@ -762,8 +780,11 @@ static int launch_train(const wost_guide* gd, const wost_records* rec, int64_t b
     if (g.dim == 2) hipLaunchKernelGGL(train_kernel<2>, dim3(grid), dim3(64), lds, s, g, a);
     else hipLaunchKernelGGL(train_kernel<3>, dim3(grid), dim3(64), lds, s, g, a);
     if (backward) {
-        hipLaunchKernelGGL(reduce_partials, dim3((a.p_mlp + 255) / 256), dim3(256), 0, s, (const float*)a.partials, grid,
-                           a.n_frag, a.p_mlp, fm, grad + gd->n_grid);
+        // rows are summed in 32 interleaved groups, each group's sums added to
+        // the gradient with atomics
+        const int ry = std::min(grid, 32);
+        hipLaunchKernelGGL(reduce_partials, dim3((a.n_frag / 4 + 255) / 256, ry), dim3(256), 0, s,
+                           (const float*)a.partials, grid, a.n_frag, fm, grad + gd->n_grid);
         if (a.n_coarse) {
             const size_t cl = sizeof(float) * (size_t)coarse_lds_floats(g, a.n_coarse);
             const int cg = coarse_scatter_grid(count);
