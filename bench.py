@@ -105,6 +105,52 @@ def cpu_baseline(scene, max_seconds=20.0):
                       % (len(pts), wpp, steps, dt)}
 
 
+MFMA_F16_PEAK = 2.5e15   # dense FP16 MFMA FLOP/s of one MI355X
+
+
+def guide_mlp_rates(W, gcfg, n_train=1 << 18, n_infer=1 << 20, reps=10):
+    """Standalone guide MLP throughput on MFMA: one Adam step on n_train
+    records and one inference of n_infer positions, timed with HIP events on
+    the launch stream.  Algorithmic FLOP: 2 P per query forward, 3 x 2 P per
+    training record (forward, data and weight gradients), P = weights of the
+    MLP (C3: 16 x 64 + 64 x 64 + 64 x 33 = 7,232)."""
+    import torch
+    g = W.Guide(gcfg, seed=3)
+    d = gcfg.dim
+    P = sum(a * b for a, b in [(gcfg.levels * gcfg.feats, gcfg.hidden)] + [(gcfg.hidden, gcfg.hidden)] *
+            (gcfg.n_hidden - 1) + [(gcfg.hidden, gcfg.n_out)])
+    rng = np.random.default_rng(9)
+    lo = np.asarray(gcfg.aabb_lo[:d]); hi = np.asarray(gcfg.aabb_hi[:d])
+    rec = W.Records(d, capacity=n_train)
+    D = np.zeros((3 * d + 5, n_train), np.float32)
+    D[0:d] = rng.uniform(lo, hi, (n_train, d)).T
+    nu = rng.normal(size=(n_train, d))
+    D[d:2 * d] = (nu / np.linalg.norm(nu, axis=1, keepdims=True)).T
+    D[3 * d] = 1.0 / (2 * np.pi)
+    D[3 * d + 4] = rng.random(n_train)
+    rec.data.copy_(torch.as_tensor(D))
+    rec.count.fill_(n_train)
+    pts = torch.as_tensor(rng.uniform(lo, hi, (n_infer, d)), dtype=torch.float32, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    out = {}
+    for name, fn, n, flop in (("train_step", lambda: g.train_step(rec, 0, n_train, loss_out=loss), n_train, 6 * P),
+                              ("infer", lambda: g.infer(pts), n_infer, 2 * P)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3 / reps
+        rate = flop * n / t
+        out[name] = {"n": n, "ms": round(t * 1e3, 4), "flop_per_item": flop, "tflops": round(rate / 1e12, 3),
+                     "mfma_f16_frac": round(rate / MFMA_F16_PEAK, 5)}
+    return out
+
+
 def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2):
     """Sampling-mode ablations (number of lobes K, the selection probability
     c: 0 = uniform, 0.5 fixed, 1 = guided only, learned) and the
@@ -172,6 +218,8 @@ def main():
     ap.add_argument("--print-walk-sha", action="store_true", help="print the walk kernel source hash and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
+    ap.add_argument("--guide-mlp", action="store_true",
+                    help="only time the standalone guide MLP (Adam step at 2^18, inference at 2^20) and exit")
     ap.add_argument("--ablations", action="store_true",
                     help="instead of the bench line: sampling-mode ablations (K, selection c) and the "
                          "training-schedule sweep on the same workload, one JSON line per configuration")
@@ -204,6 +252,9 @@ def main():
 
     torch.cuda.set_device(0)
     s = scenes.scene_c2(wpp=args.wpp)
+    if args.guide_mlp:
+        print(json.dumps({"guide_mlp": guide_mlp_rates(W, W.GuideConfig.for_scene(s))}))
+        return
     pts = torch.as_tensor(s.points, dtype=torch.float32, device="cuda")
     u = s.points[:, 0] ** 3 - 3 * s.points[:, 0] * s.points[:, 1] ** 2
     geom = W.Geometry.from_scene(s)
@@ -298,6 +349,8 @@ def main():
                 "algorithmic_bytes_per_launch": round(total_steps * bps_g / max(n_launch, 1)),
                 "walk_sources_sha256": walk_sources_sha256()[:16]}
 
+    mlp = guide_mlp_rates(W, gcfg)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(s)
@@ -322,6 +375,7 @@ def main():
                    "points": s.n_points, "wpp": args.wpp, "seed": 2410},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "guide_mlp": mlp,
         "guided": {"steps_per_s_end_to_end": round(value, 1), "walk_phase_s": round(walk_s / args.steps, 4),
                    "train_phase_s": round(train_s / args.steps, 4), "tail_phase_s": round(tail_s / args.steps, 4),
                    "time_s": round(t_g, 4), "rel_mse": rel_mse(m_g, u), "mse": mse_g, "mse_x_time": mse_g * t_g,
