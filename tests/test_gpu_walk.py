@@ -184,6 +184,38 @@ def test_query_parity_3d_sphere(W, O):
     _query_case(W, O, s, pts, dirs, 3.0)
 
 
+def test_silhouette_from_points_on_a_convex_neumann_surface(W, O):
+    """3D: points inside Neumann triangles of a geodesic sphere (Neumann on the
+    upper half), each passed as the primitive it lies on.  The surface is
+    convex, so the only silhouettes are the edges where Neumann meets
+    Dirichlet; the GPU must match the oracle's exhaustive FP64 answer with the
+    own triangle facing front.  Barycentric coordinates >= 0.05 keep the
+    points' FP32 rounding far below every neighbour's clearance."""
+    P, T = scenes.geodesic_sphere(12)
+    cen = P[T].mean(1)
+    bc = (cen[:, 2] > 0).astype(np.uint8)
+    s = rounded(scenes.Scene("sphere12", 3, P, T, bc, np.zeros((1, 3)), g=(4, np.zeros(0)), h=(4, np.zeros(0)),
+                             f=(0, np.zeros(0)), u_exact=(4, np.zeros(0))))
+    rng = np.random.default_rng(15)
+    neu = np.nonzero(s.bc == 1)[0]
+    q = neu[rng.integers(0, len(neu), 4000)].astype(np.int32)
+    w = rng.dirichlet(np.ones(3), 4000) * 0.85 + 0.05
+    V = np.asarray(s.verts, np.float64)
+    pts = np.asarray(np.einsum("ij,ijk->ik", w, V[s.prims[q]]), np.float32).astype(np.float64)
+    say("3D silhouette from boundary points", pts.shape)
+    geom = W.Geometry.from_scene(s)
+    o = O.OracleScene(s)
+    ds = geom.query(_t(pts), dirichlet=False, on_prim=q)["d_sil"].double().cpu().numpy()
+    ref = o.silhouette(pts, on_prim=q)
+    L = geom.info["diag"]
+    assert np.all(np.isfinite(ref)) and np.all(np.isfinite(ds))
+    assert np.all(np.abs(ds - ref) <= 1e-5 * ref + 2e-7 * L), np.max(np.abs(ds - ref))
+    # without the own-primitive rule the oracle sees rounding-made silhouettes
+    # next to some points: the rule is what the agreement rests on
+    plain = o.silhouette(pts)
+    say("points whose plain silhouette distance is smaller: %d" % np.sum(plain < ref - 1e-12))
+
+
 def _closed_neumann_rays(W, s, pts, targets):
     """Rays from interior points aimed (in float32) exactly at boundary
     features of a closed, all-Neumann boundary: every one must hit."""
