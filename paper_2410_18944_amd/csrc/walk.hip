@@ -489,11 +489,11 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                 });
         }
         wave_sync();
-        // the walks that step on; the closest-silhouette search runs long
-        // far from the Dirichlet boundary and on the Neumann boundary, where
-        // normal cones prune little
+        // the walks that step on; the star's queries run longer far from the
+        // Dirichlet boundary (a larger search radius) and on the Neumann
+        // boundary, where normal cones prune less
         n_step = list_long_first(L_step, N, base, lane, [&](uint32_t g) { return pv.i(F::STAT, g) == ST_STEP; },
-                                 [&](uint32_t g) { return pv.f(F::DD, g) * (pv.i(F::ONP, g) >= 0 ? 4.f : 1.f); });
+                                 [&](uint32_t g) { return pv.f(F::DD, g) * (pv.i(F::ONP, g) >= 0 ? 2.f : 1.f); });
         wave_sync();
         if (n_step == 0) continue;
 
