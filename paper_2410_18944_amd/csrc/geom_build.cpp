@@ -2,14 +2,16 @@
 // (wost_build_bvh) and their upload into caller-owned device memory.
 //
 // Three binary hierarchies are built with object-median splits along the
-// longest centroid extent (depth <= ceil(log2(n / leaf)) + 1, which bounds the
-// traversal stack):
+// longest centroid extent (depth <= ceil(log2(n / leaf)) + 1) and stored
+// four-wide: each node holds the children of a binary node, every inner
+// child replaced by its own two children (the layout is in wost_internal.h):
 //   * Dirichlet primitives  -> closest point + epsilon-shell test (Sec. 3.2)
 //   * Neumann primitives    -> first hit inside the star, visibility, and the
 //                              area-weighted Neumann sample (node measures)
 //   * Neumann silhouette candidates (2D vertices, 3D edges) with the inward
-//     normals of their adjacent Neumann primitives and per-node normal cones
-//     -> distance to the closest silhouette, which bounds the star radius
+//     normals of their adjacent Neumann primitives, per-child normal cones
+//     and, in 2D, the convex piece of the boundary each candidate is interior
+//     to -> distance to the closest silhouette, which bounds the star radius
 //     (Sec. 3.2).
 #include <algorithm>
 #include <array>
