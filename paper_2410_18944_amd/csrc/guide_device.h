@@ -26,6 +26,20 @@ namespace wost {
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+
+// c += A B over two 16-deep blocks of K at once.  The 16x16x32 FP16 MFMA pairs
+// element j of an A lane with element j of the B lanes of the same 16-lane
+// group, like the 16x16x16 form does for its four elements; handing it the
+// two 16-deep operand pairs of a lane side by side therefore adds exactly the
+// two 16x16x16 products, in one instruction.
+__device__ __forceinline__ float4_t mfma_k32(const half4_t& a0, const half4_t& a1, const half4_t& b0,
+                                             const half4_t& b1, const float4_t& c)
+{
+    const half8_t a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const half8_t b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
 
 constexpr int kMaxLevels = 16;
 constexpr int kMaxLayers = 6;
@@ -168,9 +182,13 @@ __device__ void guide_forward_wave(const GuideDev& g, const float* x, float* lds
             for (int mb = 0; mb < 4; ++mb) {
                 float4_t c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int kb = 0; kb < 4; ++kb)
-                    if (kb < KB)
+                for (int kb = 0; kb < 4; kb += 2) {
+                    if (kb + 1 < KB)
+                        c = mfma_k32(A[(mb * KB + kb) * 64 + lane], A[(mb * KB + kb + 1) * 64 + lane], act[kb],
+                                     act[kb + 1], c);
+                    else if (kb < KB)
                         c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
+                }
                 half4_t h;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) h[i] = (_Float16)fmaxf(c[i], 0.f);
@@ -187,9 +205,13 @@ __device__ void guide_forward_wave(const GuideDev& g, const float* x, float* lds
             for (int mb = 0; mb < g.mb[layer]; ++mb) {
                 float4_t c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int kb = 0; kb < 4; ++kb)
-                    if (kb < KB)
+                for (int kb = 0; kb < 4; kb += 2) {
+                    if (kb + 1 < KB)
+                        c = mfma_k32(A[(mb * KB + kb) * 64 + lane], A[(mb * KB + kb + 1) * 64 + lane], act[kb],
+                                     act[kb + 1], c);
+                    else if (kb < KB)
                         c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
+                }
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int j = 16 * mb + 4 * g4 + i;
