@@ -237,9 +237,9 @@ int64_t wost_guide_param_count(const wost_guide* g);
  * same order, MLP weights re-arranged into MFMA operand fragments). */
 int64_t wost_guide_shadow_bytes(const wost_guide* g);
 /* Bind caller-owned device storage: master float32 [P], shadow
- * [wost_guide_shadow_bytes] (8-byte aligned), Adam moments m, v float32 [P],
- * gradient float32 [P].  Any of adam_m/adam_v/grad may be NULL for
- * inference-only use.  Pointers must stay valid while the guide is used. */
+ * [wost_guide_shadow_bytes] (16-byte aligned, else WOST_EINVAL), Adam moments
+ * m, v float32 [P], gradient float32 [P].  Any of adam_m/adam_v/grad may be
+ * NULL for inference-only use.  Pointers must stay valid while the guide is used. */
 int wost_guide_bind(wost_guide* g, float* master, void* shadow_f16, float* adam_m, float* adam_v,
                     float* grad);
 /* Seeded initialisation of master, shadow, and zeroing of Adam state:

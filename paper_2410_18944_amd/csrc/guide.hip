@@ -20,7 +20,7 @@ int guide_prepare(const wost_guide* g, int dim, GuideDev& out)
     if (!g->shadow) { set_error("guide: parameters not bound"); return WOST_ESTATE; }
     out = g->dev;
     out.grid = (const uint32_t*)g->shadow;
-    out.frags = (const half4_t*)((const _Float16*)g->shadow + g->n_grid);
+    out.frags = (const half4_t*)((const _Float16*)g->shadow + g->frag_base);
     return WOST_OK;
 }
 
@@ -123,6 +123,8 @@ extern "C" int wost_guide_create(const wost_guide_config* c, wost_guide** out)
         d.inv_ext[i] = i < c->dim ? 1.f / (c->aabb_hi[i] - c->aabb_lo[i]) : 0.f;
     }
     g->n_grid = (int64_t)c->levels * (1ll << c->log2_table) * c->feats;
+    // fragments start on a 16-byte boundary (paired fragments are read as one 16-byte load)
+    g->frag_base = (g->n_grid + 7) & ~(int64_t)7;
     // layers
     const int n_layers = c->n_hidden + 1;
     d.n_layers = n_layers;
@@ -155,13 +157,13 @@ extern "C" int64_t wost_guide_param_count(const wost_guide* g) { return g ? g->n
 
 extern "C" int64_t wost_guide_shadow_bytes(const wost_guide* g)
 {
-    return g ? 2 * (g->n_grid + g->n_frag_halves) : -1;
+    return g ? 2 * (g->frag_base + g->n_frag_halves) : -1;
 }
 
 extern "C" int wost_guide_bind(wost_guide* g, float* master, void* shadow, float* m, float* v, float* grad)
 {
     if (!g || !master || !shadow) { set_error("wost_guide_bind: master and shadow are required"); return WOST_EINVAL; }
-    if (((uintptr_t)shadow) & 7) { set_error("wost_guide_bind: shadow must be 8-byte aligned"); return WOST_EINVAL; }
+    if (((uintptr_t)shadow) & 15) { set_error("wost_guide_bind: shadow must be 16-byte aligned"); return WOST_EINVAL; }
     g->master = master;
     g->shadow = shadow;
     g->adam_m = m;
@@ -194,15 +196,19 @@ __global__ void init_params_kernel2(float* master, int64_t n_grid, int64_t n_tot
     master[i] = u * sqrtf(6.f / (float)t.in[l]);
 }
 
-__global__ void sync_shadow_kernel2(const float* master, _Float16* shadow, int64_t n_grid, GuideDev g, LayerTabs t,
-                                    int64_t n_frag_halves)
+__global__ void sync_shadow_kernel2(const float* master, _Float16* shadow, int64_t n_grid, int64_t frag_base,
+                                    GuideDev g, LayerTabs t, int64_t n_frag_halves)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_grid) {
         shadow[i] = (_Float16)master[i];
         return;
     }
-    const int64_t f = i - n_grid;
+    if (i < frag_base) {
+        shadow[i] = (_Float16)0.f;  // alignment padding
+        return;
+    }
+    const int64_t f = i - frag_base;
     if (f >= n_frag_halves) return;
     int64_t frag = f >> 2;
     const int e = (int)(f & 3);
@@ -211,20 +217,27 @@ __global__ void sync_shadow_kernel2(const float* master, _Float16* shadow, int64
     if (bwd) frag -= n_fwd;
     int l = 0;
     while (l + 1 < g.n_layers && frag >= g.frag_off[l + 1]) ++l;
-    const int64_t rel = frag - g.frag_off[l];
-    const int lane = (int)(rel & 63);
-    const int blk = (int)(rel >> 6);
+    const int rel = (int)(frag - g.frag_off[l]);
+    // forward blocks run along the input features, backward blocks along the
+    // output features; invert frag_index for this layer's block count
+    const int KB = bwd ? g.mb[l] : g.kb[l];
+    const int blk = rel >> 6;
+    const int mb = blk / KB;
+    int kb = blk - mb * KB, lane;
+    if ((kb | 1) < KB) {
+        const int q = rel - (mb * KB + (kb & ~1)) * 64;
+        kb = (kb & ~1) + (q & 1);
+        lane = q >> 1;
+    } else {
+        lane = rel & 63;
+    }
     int row, colo;
     if (!bwd) {
         // forward A = W^T: m = output feature (16 mb + lane%16), k = input feature
-        const int KB = g.kb[l];
-        const int mb = blk / KB, kb = blk - mb * KB;
         row = 16 * kb + 4 * (lane >> 4) + e;
         colo = 16 * mb + (lane & 15);
     } else {
         // backward A = W: m = input feature (16 mb + lane%16), k = output feature
-        const int KB = g.mb[l];            // output blocks
-        const int mb = blk / KB, kb = blk - mb * KB;
         row = 16 * mb + (lane & 15);
         colo = 16 * kb + 4 * (lane >> 4) + e;
     }
@@ -249,9 +262,9 @@ extern "C" int wost_guide_sync_shadow(wost_guide* g, void* stream)
 {
     if (!g || !g->master || !g->shadow) { set_error("wost_guide_sync_shadow: guide not bound"); return WOST_ESTATE; }
     hipStream_t s = (hipStream_t)stream;
-    const int64_t n = g->n_grid + g->n_frag_halves;
+    const int64_t n = g->frag_base + g->n_frag_halves;
     hipLaunchKernelGGL(sync_shadow_kernel2, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g->master,
-                       (_Float16*)g->shadow, g->n_grid, g->dev, tabs_of(g), g->n_frag_halves);
+                       (_Float16*)g->shadow, g->n_grid, g->frag_base, g->dev, tabs_of(g), g->n_frag_halves);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("wost_guide_sync_shadow: %s", hipGetErrorString(e)); return WOST_EHIP; }
     return WOST_OK;

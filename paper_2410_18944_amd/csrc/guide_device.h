@@ -33,12 +33,51 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 // group, like the 16x16x16 form does for its four elements; handing it the
 // two 16-deep operand pairs of a lane side by side therefore adds exactly the
 // two 16x16x16 products, in one instruction.
-__device__ __forceinline__ float4_t mfma_k32(const half4_t& a0, const half4_t& a1, const half4_t& b0,
-                                             const half4_t& b1, const float4_t& c)
+__device__ __forceinline__ float4_t mfma_k32(const half8_t& a, const half8_t& b, const float4_t& c)
 {
-    const half8_t a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
-    const half8_t b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float4_t mfma_k16(const half4_t& a, const half4_t& b, const float4_t& c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ half4_t half_lo(const half8_t& v) { return {v[0], v[1], v[2], v[3]}; }
+__device__ __forceinline__ half4_t half_hi(const half8_t& v) { return {v[4], v[5], v[6], v[7]}; }
+
+// writes h into the low (hi = 0) or high four elements of v
+__device__ __forceinline__ void put_half(half8_t& v, int hi, const half4_t& h)
+{
+    if (hi) {
+        v[4] = h[0]; v[5] = h[1]; v[6] = h[2]; v[7] = h[3];
+    } else {
+        v[0] = h[0]; v[1] = h[1]; v[2] = h[2]; v[3] = h[3];
+    }
+}
+
+// Operand fragment layout of one layer (in units of one lane's four halves):
+// block (mb, kb) of a layer with KB blocks along K.  The blocks 2j and 2j + 1
+// of a row block are interleaved lane by lane, so a lane reads both with one
+// 16-byte load; an unpaired last block keeps 64 consecutive fragments.
+__host__ __device__ __forceinline__ int frag_index(int mb, int kb, int KB, int lane)
+{
+    return ((kb | 1) < KB) ? (mb * KB + (kb & ~1)) * 64 + 2 * lane + (kb & 1) : (mb * KB + kb) * 64 + lane;
+}
+
+// A x B over K = 16 KB for the 16x16 output block mb: B is held as pairs of
+// 16-deep fragments (pair p = blocks 2p, 2p + 1), at most four blocks.
+__device__ __forceinline__ float4_t mfma_row_block(const half4_t* A, int mb, int KB, int lane, const half8_t* b,
+                                                   float4_t c)
+{
+#pragma unroll
+    for (int kb = 0; kb < 4; kb += 2) {
+        if (kb + 1 < KB)
+            c = mfma_k32(*(const half8_t*)(A + frag_index(mb, kb, KB, lane)), b[kb >> 1], c);
+        else if (kb < KB)
+            c = mfma_k16(A[frag_index(mb, kb, KB, lane)], half_lo(b[kb >> 1]), c);
+    }
+    return c;
 }
 
 constexpr int kMaxLevels = 16;
@@ -159,7 +198,7 @@ __device__ void guide_forward_wave(const GuideDev& g, const float* x, float* lds
 #pragma unroll
         for (int i = 0; i < D; ++i) xw[i] = __shfl(x[i], w);
         normalise_input<D>(g, xw, xh);
-        half4_t act[4];
+        half8_t act[2];
         const int kb0 = g.kb[0];
         // every loop over the four 16-feature blocks is unrolled with a guard,
         // so the activation fragments stay in registers
@@ -171,31 +210,23 @@ __device__ void guide_forward_wave(const GuideDev& g, const float* x, float* lds
             const float2 f1 = grid_level<D>(g, l0 + 1, xh);
             half4_t h;
             h[0] = (_Float16)f0.x; h[1] = (_Float16)f0.y; h[2] = (_Float16)f1.x; h[3] = (_Float16)f1.y;
-            act[kb] = h;
+            put_half(act[kb >> 1], kb & 1, h);
         }
         // hidden layers
         for (int layer = 0; layer + 1 < g.n_layers; ++layer) {
             const half4_t* A = g.frags + g.frag_off[layer];
             const int KB = g.kb[layer];
-            half4_t nxt[4];
+            half8_t nxt[2];
 #pragma unroll
             for (int mb = 0; mb < 4; ++mb) {
-                float4_t c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kb = 0; kb < 4; kb += 2) {
-                    if (kb + 1 < KB)
-                        c = mfma_k32(A[(mb * KB + kb) * 64 + lane], A[(mb * KB + kb + 1) * 64 + lane], act[kb],
-                                     act[kb + 1], c);
-                    else if (kb < KB)
-                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
-                }
+                const float4_t c = mfma_row_block(A, mb, KB, lane, act, float4_t{0.f, 0.f, 0.f, 0.f});
                 half4_t h;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) h[i] = (_Float16)fmaxf(c[i], 0.f);
-                nxt[mb] = h;
+                put_half(nxt[mb >> 1], mb & 1, h);
             }
-#pragma unroll
-            for (int mb = 0; mb < 4; ++mb) act[mb] = nxt[mb];
+            act[0] = nxt[0];
+            act[1] = nxt[1];
         }
         // output layer -> LDS, transposed to [walk][output]
         {
@@ -203,15 +234,7 @@ __device__ void guide_forward_wave(const GuideDev& g, const float* x, float* lds
             const half4_t* A = g.frags + g.frag_off[layer];
             const int KB = g.kb[layer];
             for (int mb = 0; mb < g.mb[layer]; ++mb) {
-                float4_t c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kb = 0; kb < 4; kb += 2) {
-                    if (kb + 1 < KB)
-                        c = mfma_k32(A[(mb * KB + kb) * 64 + lane], A[(mb * KB + kb + 1) * 64 + lane], act[kb],
-                                     act[kb + 1], c);
-                    else if (kb < KB)
-                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
-                }
+                const float4_t c = mfma_row_block(A, mb, KB, lane, act, float4_t{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int j = 16 * mb + 4 * g4 + i;

@@ -7,6 +7,7 @@ struct wost_guide {
     wost_guide_config cfg;
     wost::GuideDev dev;             // static part (pointers filled by guide_prepare)
     int64_t n_grid = 0;             // grid parameters (L * T * F)
+    int64_t frag_base = 0;          // first MLP fragment half in the shadow (multiple of 8)
     int64_t n_params = 0;           // grid + MLP parameters
     int64_t n_frag_halves = 0;      // swizzled MLP fragment halves in the shadow
     int64_t layer_off[wost::kMaxLayers] = {};

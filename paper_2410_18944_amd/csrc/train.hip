@@ -261,14 +261,16 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
 #pragma unroll
             for (int d = 0; d < D; ++d) xw[d] = __shfl(x[d], w);
             normalise_input<D>(g, xw, xh);
-            half4_t act[4];
-            for (int kb = 0; kb < kb0; ++kb) {
+            half8_t act[2];
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) {
+                if (kb >= kb0) break;
                 const int l0 = 8 * kb + 2 * g4;
                 const float2 f0 = grid_level<D>(g, l0, xh);
                 const float2 f1 = grid_level<D>(g, l0 + 1, xh);
                 half4_t h;
                 h[0] = (_Float16)f0.x; h[1] = (_Float16)f0.y; h[2] = (_Float16)f1.x; h[3] = (_Float16)f1.y;
-                act[kb] = h;
+                put_half(act[kb >> 1], kb & 1, h);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) s_act[(16 * kb + 4 * g4 + e) * 64 + w] = h[e];
             }
@@ -276,21 +278,19 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
             for (int layer = 0; layer + 1 < L; ++layer) {
                 const half4_t* A = g.frags + g.frag_off[layer];
                 const int KB = g.kb[layer];
-                half4_t nxt[4];
+                half8_t nxt[2];
 #pragma unroll
                 for (int mb = 0; mb < 4; ++mb) {
-                    float4_t c = {0.f, 0.f, 0.f, 0.f};
-                    for (int kb = 0; kb < KB; ++kb)
-                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
+                    const float4_t c = mfma_row_block(A, mb, KB, lane, act, float4_t{0.f, 0.f, 0.f, 0.f});
                     half4_t h;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) h[e] = (_Float16)fmaxf(c[e], 0.f);
-                    nxt[mb] = h;
+                    put_half(nxt[mb >> 1], mb & 1, h);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) s_act[(row_off + 16 * mb + 4 * g4 + e) * 64 + w] = h[e];
                 }
-#pragma unroll
-                for (int mb = 0; mb < 4; ++mb) act[mb] = nxt[mb];
+                act[0] = nxt[0];
+                act[1] = nxt[1];
                 row_off += 64;
             }
             {
@@ -298,9 +298,7 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
                 const half4_t* A = g.frags + g.frag_off[layer];
                 const int KB = g.kb[layer];
                 for (int mb = 0; mb < g.mb[layer]; ++mb) {
-                    float4_t c = {0.f, 0.f, 0.f, 0.f};
-                    for (int kb = 0; kb < KB; ++kb)
-                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(A[(mb * KB + kb) * 64 + lane], act[kb], c, 0, 0, 0);
+                    const float4_t c = mfma_row_block(A, mb, KB, lane, act, float4_t{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
                     for (int e = 0; e < 4; ++e) s_y[w * ystride + 16 * mb + 4 * g4 + e] = c[e];
                 }
@@ -340,10 +338,15 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
                 for (int nb = 0; nb < rows_in / 16; ++nb) {
                     float4_t c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const half4_t Av = lds_h4(cur + (16 * mb + col) * 64 + 16 * kk + 4 * g4);
-                        const half4_t Bv = lds_h4(act + (16 * nb + col) * 64 + 16 * kk + 4 * g4);
-                        c = __builtin_amdgcn_mfma_f32_16x16x16f16(Av, Bv, c, 0, 0, 0);
+                    for (int kk = 0; kk < 4; kk += 2) {
+                        const _Float16* const ap = cur + (16 * mb + col) * 64 + 16 * kk + 4 * g4;
+                        const _Float16* const bp = act + (16 * nb + col) * 64 + 16 * kk + 4 * g4;
+                        half8_t av, bv;
+                        put_half(av, 0, lds_h4(ap));
+                        put_half(av, 1, lds_h4(ap + 16));
+                        put_half(bv, 0, lds_h4(bp));
+                        put_half(bv, 1, lds_h4(bp + 16));
+                        c = mfma_k32(av, bv, c);
                     }
                     float4* const dst = prow + (a.blk_off[layer] + mb * (rows_in / 16) + nb) * 64 + lane;
                     float4 v = *dst;
@@ -365,11 +368,21 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
                 for (int mb = 0; mb < 4; ++mb) {
                     float4_t c = {0.f, 0.f, 0.f, 0.f};
                     if (mb < MBi) {
-                        for (int kb = 0; kb < KBo; ++kb) {
-                            half4_t Bv;
+                        int kb = 0;
+                        for (; kb + 1 < KBo; kb += 2) {
+                            half8_t bv;
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) Bv[e] = cur[(16 * kb + 4 * g4 + e) * 64 + 16 * cb + col];
-                            c = __builtin_amdgcn_mfma_f32_16x16x16f16(Bw[(mb * KBo + kb) * 64 + lane], Bv, c, 0, 0, 0);
+                            for (int e = 0; e < 4; ++e) {
+                                bv[e] = cur[(16 * kb + 4 * g4 + e) * 64 + 16 * cb + col];
+                                bv[4 + e] = cur[(16 * kb + 16 + 4 * g4 + e) * 64 + 16 * cb + col];
+                            }
+                            c = mfma_k32(*(const half8_t*)(Bw + frag_index(mb, kb, KBo, lane)), bv, c);
+                        }
+                        if (kb < KBo) {
+                            half4_t bv;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) bv[e] = cur[(16 * kb + 4 * g4 + e) * 64 + 16 * cb + col];
+                            c = mfma_k16(Bw[frag_index(mb, kb, KBo, lane)], bv, c);
                         }
                         if (layer > 0) {
 #pragma unroll
