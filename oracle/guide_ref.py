@@ -8,7 +8,10 @@ Philox words.
 Contents
 * von Mises-Fisher density in 2D/3D and the K-lobe mixture (Sec. 3.3, "vmm").
 * Normalization mapping of the network outputs (Sec. 4.2, Tab. "reg_map").
-* Reflected guiding pdf on a Neumann boundary (Sec. 4.3).
+* Reflected guiding pdf on a Neumann boundary (Sec. 4.3), and the variant
+  without reflection of the reflection ablation (Sec. 6, "Sample Reflection at
+  Neumann Boundaries"): the mixture itself on the valid half, a guided draw
+  into the wall scoring zero.
 * Uniform directional pdf (Sec. 4.1) and the one-sample MIS pdf (Sec. 4.4,
   "mis_pdf").
 * Samplers: 2D von Mises by Best & Fisher's wrapped-Cauchy rejection method;
@@ -73,13 +76,17 @@ def reflect(nu, n):
     return nu - 2.0 * np.sum(nu * n, axis=-1, keepdims=True) * n
 
 
-def guiding_pdf(nu, mu, kappa, lam, on_neumann=False, n=None):
+def guiding_pdf(nu, mu, kappa, lam, on_neumann=False, n=None, reflected=True):
     """p_g: the mixture off the Neumann boundary; on it, V(nu)+V(nu^-) on the
-    valid half (nu.n > 0) and 0 elsewhere (Sec. 4.3)."""
+    valid half (nu.n > 0) and 0 elsewhere (Sec. 4.3).  Without reflection
+    (``reflected=False``) it is V(nu) on the valid half: the mass V puts on the
+    invalid half is the probability of a draw into the wall."""
     if not on_neumann:
         return mixture_pdf(nu, mu, kappa, lam)
     cn = np.sum(nu * n, axis=-1)
-    val = mixture_pdf(nu, mu, kappa, lam) + mixture_pdf(reflect(nu, n), mu, kappa, lam)
+    val = mixture_pdf(nu, mu, kappa, lam)
+    if reflected:
+        val = val + mixture_pdf(reflect(nu, n), mu, kappa, lam)
     return np.where(cn > 0, val, 0.0)
 
 
@@ -92,9 +99,10 @@ def uniform_pdf(nu, d, on_neumann=False, n=None):
     return np.where(np.sum(nu * n, axis=-1) > 0, 2.0 * base, 0.0)
 
 
-def mis_pdf(nu, mu, kappa, lam, c, d, on_neumann=False, n=None):
+def mis_pdf(nu, mu, kappa, lam, c, d, on_neumann=False, n=None, reflected=True):
     """p~ = c p_g + (1 - c) p_u  (Sec. 4.4, balance heuristic, one sample)."""
-    return c * guiding_pdf(nu, mu, kappa, lam, on_neumann, n) + (1 - c) * uniform_pdf(nu, d, on_neumann, n)
+    return (c * guiding_pdf(nu, mu, kappa, lam, on_neumann, n, reflected)
+            + (1 - c) * uniform_pdf(nu, d, on_neumann, n))
 
 
 def map_outputs(y, d, K):
@@ -170,13 +178,16 @@ def uniform_direction(d, u0, u1):
     return np.array([rr * math.cos(ph), rr * math.sin(ph), z])
 
 
-def sample_direction(d, mu, kappa, lam, c, block0, block3, bf_blocks, on_neumann=False, n=None):
+def sample_direction(d, mu, kappa, lam, c, block0, block3, bf_blocks, on_neumann=False, n=None, reflected=True):
     """One MIS draw (Sec. 4.4): with probability c pick lobe i ~ lam and draw
     from vMF(mu_i, kappa_i), else draw uniformly; on a Neumann boundary reflect
     an invalid draw about the tangent plane (Sec. 4.3).  ``block0`` = uniforms
     (dir0, dir1, mis, lobe); ``block3`` = (src_dir1, eta, phi, unused);
     ``bf_blocks`` = per-iteration (U1, U2, U3) for the 2D rejection loop.
-    Returns (nu, p~(nu), guided_branch)."""
+    Returns (nu, p~(nu), guided_branch).
+    With ``reflected=False`` a guided draw with nu.n <= 0 is not reflected: it
+    is returned as drawn with p~ = 0, which marks a sample whose recursive term
+    is zero.  Uniform draws keep using the valid half, as in plain WoSt."""
     u_dir0, u_dir1, u_mis, u_lobe = block0
     guided = u_mis < c
     if guided:
@@ -194,9 +205,11 @@ def sample_direction(d, mu, kappa, lam, c, block0, block3, bf_blocks, on_neumann
         nu = uniform_direction(d, u_dir0, u_dir1)
     if on_neumann:
         cn = float(np.dot(nu, n))
+        if guided and not reflected and cn <= 0:
+            return nu, 0.0, guided
         if cn < 0:
             nu = nu - 2.0 * cn * n
-    p = mis_pdf(nu, mu, kappa, lam, c, d, on_neumann, n)
+    p = mis_pdf(nu, mu, kappa, lam, c, d, on_neumann, n, reflected)
     return nu, float(p), guided
 
 
@@ -344,13 +357,15 @@ def log_vmf_t(nu, mu, kappa, d):
     return torch.log(kappa) - math.log(2 * math.pi) - torch.log(-torch.expm1(-2.0 * kappa)) + kappa * (c - 1.0)
 
 
-def loss_per_sample(cfg: GuideConfig, y, nu, n_in, on_n, p_sample, p_t, e=E_MIS, pg_fixed=None):
+def loss_per_sample(cfg: GuideConfig, y, nu, n_in, on_n, p_sample, p_t, e=E_MIS, pg_fixed=None, reflected=True):
     """Surrogate whose gradients are the paper's one-sample estimators:
     l = -w [ log p_g(nu | Theta) + e log( c sg(p_g) + (1-c) p_u ) ],  w = p_t / p~_sample.
     d l / d Theta = -p_t grad p_g / (p~ p_g)        ("one_sample_kld"),
     d l / d c     = -e p_t (p_g - p_u) / p~^2        ("one_sample_sp").
     y [n, n_out] torch (requires grad), the rest numpy.  ``pg_fixed`` replaces
-    sg(p_g) by given constants (for finite-difference checks of the gradient)."""
+    sg(p_g) by given constants (for finite-difference checks of the gradient).
+    ``reflected`` selects the guiding pdf on Neumann records: the reflected
+    mixture (Sec. 4.3) or, without reflection, the plain mixture."""
     d, K = cfg.dim, cfg.K
     nu_t, n_t = _t(nu), _t(n_in)
     on = torch.as_tensor(np.asarray(on_n, bool))
@@ -365,7 +380,7 @@ def loss_per_sample(cfg: GuideConfig, y, nu, n_in, on_n, p_sample, p_t, e=E_MIS,
     l2 = loglam + log_vmf_t(nu_r[:, None, :], mu, kappa, d)
     both = torch.logsumexp(torch.cat([l1, l2], dim=1), dim=1)
     one = torch.logsumexp(l1, dim=1)
-    log_pg = torch.where(on, both, one)
+    log_pg = torch.where(on, both, one) if reflected else one
     area = sphere_area(d)
     pu = torch.where(on, torch.full_like(log_pg, 2.0 / area), torch.full_like(log_pg, 1.0 / area))
     log_pg_sg = log_pg.detach() if pg_fixed is None else torch.log(_t(pg_fixed))

@@ -159,6 +159,65 @@ def test_onb_is_orthonormal():
         np.testing.assert_allclose(M @ M.T, np.eye(3), atol=1e-12)
 
 
+def test_unreflected_pdf_mass_is_von_mises_valid_half_mass():
+    """Without reflection p_g on a wall is the mixture restricted to the valid
+    half: its integral is sum_i lam_i P_i(valid), P_i from scipy's von Mises
+    CDF; the MIS pdf integrates to 1 - c (1 - that mass), the probability that
+    a draw is not wasted."""
+    rng = np.random.default_rng(77)
+    mu, kappa, lam = _rand_theta(rng, 2, 5, (0.3, 25.0))
+    tn = 0.8
+    n = np.array([math.cos(tn), math.sin(tn)])
+    valid = 0.0
+    for m, k, l in zip(mu, kappa, lam):
+        tm = math.atan2(m[1], m[0])
+        valid += l * (stats.vonmises.cdf(tn + math.pi / 2, k, loc=tm) - stats.vonmises.cdf(tn - math.pi / 2, k, loc=tm))
+    def arc(f, a, b):
+        return integrate.quad(lambda t: float(f(np.array([[math.cos(t), math.sin(t)]]))[0]), a, b,
+                              epsabs=1e-12, epsrel=1e-12, limit=200)[0]
+
+    pg = lambda v: G.guiding_pdf(v, mu, kappa, lam, True, n, reflected=False)
+    got = arc(pg, tn - math.pi / 2, tn + math.pi / 2)
+    assert got == pytest.approx(valid, abs=1e-9)
+    assert arc(pg, tn + math.pi / 2, tn + 1.5 * math.pi) == 0.0
+    assert valid < 0.999  # some mass lies in the wall, else the pin proves nothing
+    c = 0.6
+    tot = arc(lambda v: G.mis_pdf(v, mu, kappa, lam, c, 2, True, n, reflected=False), tn - math.pi / 2,
+              tn + math.pi / 2)
+    assert tot == pytest.approx(1 - c * (1 - valid), abs=1e-9)
+    # the reflected pdf keeps all the mass
+    assert arc(lambda v: G.guiding_pdf(v, mu, kappa, lam, True, n), tn - math.pi / 2,
+               tn + math.pi / 2) == pytest.approx(1.0, abs=1e-9)
+
+
+def test_unreflected_draws_hit_the_wall_with_the_invalid_mass():
+    """The fraction of wasted draws is c times the mixture mass on the invalid
+    half (2D, scipy's von Mises CDF); every non-wasted draw lies in the valid
+    half and carries the MIS pdf of the unreflected mixture."""
+    rng = np.random.default_rng(78)
+    mu, kappa, lam = _rand_theta(rng, 2, 3, (0.5, 10.0))
+    tn = -0.3
+    n = np.array([math.cos(tn), math.sin(tn)])
+    inval = 0.0
+    for m, k, l in zip(mu, kappa, lam):
+        tm = math.atan2(m[1], m[0])
+        inval += l * (1 - (stats.vonmises.cdf(tn + math.pi / 2, k, loc=tm)
+                           - stats.vonmises.cdf(tn - math.pi / 2, k, loc=tm)))
+    c = 0.7
+    N = 8000
+    wall = 0
+    for _ in range(N):
+        nu, p, g = G.sample_direction(2, mu, kappa, lam, c, rng.random(4), rng.random(4), rng.random((64, 3)),
+                                      True, n, reflected=False)
+        if p == 0.0:
+            wall += 1
+        else:
+            assert np.dot(nu, n) >= 0
+            assert p == pytest.approx(G.mis_pdf(nu, mu, kappa, lam, c, 2, True, n, reflected=False), rel=1e-12)
+    q = c * inval
+    assert abs(wall / N - q) < 5 * math.sqrt(q * (1 - q) / N), (wall / N, q)
+
+
 @pytest.mark.parametrize("d", [2, 3])
 def test_mis_draw_branch_and_lobe_frequencies(d):
     rng = np.random.default_rng(20 + d)
@@ -203,12 +262,14 @@ def _harmonic(d):
 
 
 @pytest.mark.parametrize("d", [2, 3])
-@pytest.mark.parametrize("on_wall", [False, True])
-def test_mean_value_property_guided_mis(d, on_wall):
+@pytest.mark.parametrize("on_wall,reflected", [(False, True), (True, True), (True, False)])
+def test_mean_value_property_guided_mis(d, on_wall, reflected):
     """E[ u(x + r nu) / (|S| alpha p~(nu)) ] = u(x) for harmonic u, with nu drawn
     from the MIS mixture of a random guide (reflected on a wall, alpha = 1/2;
-    the wall normal is chosen so that du/dn = 0 on it, i.e. no Neumann term)."""
-    rng = np.random.default_rng(100 + d + 10 * on_wall)
+    the wall normal is chosen so that du/dn = 0 on it, i.e. no Neumann term).
+    Without reflection a guided draw into the wall scores zero, and the
+    estimate must stay unbiased."""
+    rng = np.random.default_rng(100 + d + 10 * on_wall + 20 * (not reflected))
     mu, kappa, lam = _rand_theta(rng, d, 8, (0.5, 20))
     c = 0.7
     u = _harmonic(d)
@@ -224,12 +285,20 @@ def test_mean_value_property_guided_mis(d, on_wall):
     r = 0.5
     N = 40000
     vals = np.empty(N)
+    n_wall = 0
     for i in range(N):
-        nu, p, _ = G.sample_direction(d, mu, kappa, lam, c, rng.random(4), rng.random(4), rng.random((64, 3)),
-                                      on_wall, n)
-        vals[i] = u(x + r * nu) / (G.sphere_area(d) * alpha * p)
+        nu, p, g = G.sample_direction(d, mu, kappa, lam, c, rng.random(4), rng.random(4), rng.random((64, 3)),
+                                      on_wall, n, reflected)
+        if p == 0.0:
+            assert g and not reflected and np.dot(nu, n) <= 0
+            n_wall += 1
+            vals[i] = 0.0
+        else:
+            vals[i] = u(x + r * nu) / (G.sphere_area(d) * alpha * p)
     est, se = vals.mean(), vals.std() / math.sqrt(N)
     assert abs(est - u(x)) < 5 * se, (est, u(x), se)
+    if not reflected:
+        assert n_wall > 0.01 * N
 
 
 # ----------------------------------------------------------------------------- network + loss
@@ -319,7 +388,8 @@ def test_loss_gradient_matches_central_differences(d):
 
 
 @pytest.mark.parametrize("d", [2, 3])
-def test_surrogate_gradients_equal_one_sample_estimators(d):
+@pytest.mark.parametrize("reflected", [True, False])
+def test_surrogate_gradients_equal_one_sample_estimators(d, reflected):
     """Autograd of the surrogate w.r.t. the mapped parameters equals the paper's
     one-sample KL gradient -p_t grad p_g / (p~ p_g) (evaluated here by central
     differences of the plain numpy pdf) and the selection-probability gradient
@@ -331,12 +401,12 @@ def test_surrogate_gradients_equal_one_sample_estimators(d):
     y = rng.standard_normal((n, K * (d + 2) + 1))
     x, nu, nrm, on, p_s, p_t = _train_batch(cfg, rng, n)
     yt = torch.tensor(y, requires_grad=True)
-    G.loss_per_sample(cfg, yt, nu, nrm, on, p_s, p_t).sum().backward()
+    G.loss_per_sample(cfg, yt, nu, nrm, on, p_s, p_t, reflected=reflected).sum().backward()
     gy = yt.grad.numpy()
 
     def pg_of(yrow, i):
         mu, kappa, lam, c = G.map_outputs(yrow[None], d, K)
-        return float(G.guiding_pdf(nu[i][None], mu[0], kappa[0], lam[0], bool(on[i]), nrm[i])[0])
+        return float(G.guiding_pdf(nu[i][None], mu[0], kappa[0], lam[0], bool(on[i]), nrm[i], reflected)[0])
 
     for i in range(n):
         pg = pg_of(y[i], i)
