@@ -153,7 +153,8 @@ def guide_mlp_rates(W, gcfg, n_train=1 << 18, n_infer=1 << 20, reps=10):
 
 def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2):
     """Sampling-mode ablations (number of lobes K, the selection probability
-    c: 0 = uniform, 0.5 fixed, 1 = guided only, learned) and the
+    c: 0 = uniform, 0.5 fixed, 1 = guided only, learned; sample reflection at
+    Neumann points on or off) and the
     training-schedule sweep (how many walks per point train the guide, Adam
     steps per batch), each a full solve of the bench workload; mean of `reps`
     seeds.  Prints one JSON line per configuration."""
@@ -175,6 +176,7 @@ def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2
             else:
                 pb = W.Problem.from_scene(s, sampling=sampling, reflect=reflect, c_fixed=c_fixed)
                 g = W.Guide(W.GuideConfig.for_scene(s, K=K), seed=seed)
+                g.reflect = reflect
                 sched = OnlineSchedule(batch_wpp=args.batch_wpp, train_until_wpp=until, max_steps_per_batch=steps)
                 e0.record()
                 acc, info = online_solve(geom, pb, pts, args.wpp, g, sched, seed=18944 + seed)
@@ -198,6 +200,7 @@ def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2
     one("MIS, c = 0.5 fixed", sampling="mis_fixed", c_fixed=0.5)
     one("guided only (c = 1)", sampling="guided_only")
     one("MIS, learned c (default)")
+    one("learned c, no reflection", reflect=False)
     for K in (4, 16):
         one("learned c, K = %d" % K, K=K)
     for until in (128, 256):
@@ -221,7 +224,7 @@ def main():
     ap.add_argument("--guide-mlp", action="store_true",
                     help="only time the standalone guide MLP (Adam step at 2^18, inference at 2^20) and exit")
     ap.add_argument("--ablations", action="store_true",
-                    help="instead of the bench line: sampling-mode ablations (K, selection c) and the "
+                    help="instead of the bench line: sampling-mode ablations (K, selection c, reflection) and the "
                          "training-schedule sweep on the same workload, one JSON line per configuration")
     args = ap.parse_args()
     if args.print_walk_sha:

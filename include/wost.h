@@ -150,16 +150,22 @@ typedef struct {
     float rr_q;             /* roulette survival probability                             */
     int32_t sampling;       /* WOST_SAMPLING_*                                           */
     float c_fixed;          /* selection probability for WOST_SAMPLING_MIS_FIXED         */
-    int32_t reflect;        /* must be 1 for guided sampling: draws into the wall at a
-                               Neumann point are reflected (Sec. 4.3); uniform
-                               draws there always use the valid half             */
+    int32_t reflect;        /* guided draws into the wall at a Neumann point:
+                               1 = reflected about the tangent plane (Sec. 4.3),
+                               0 = wasted (the walk ends there with zero
+                               recursive term; the reflection ablation of
+                               Sec. 6).  Guided solves require it to equal the
+                               guide's setting (wost_guide_set_reflect), else
+                               WOST_EINVAL.  Uniform draws always use the valid
+                               half                                              */
 } wost_problem;
 
 /* Training records written by guided walks (one per drawn direction), in a
  * caller-owned device buffer of `capacity` rows, structure-of-arrays:
  * field f of row i is at data[f * capacity + i].  Fields (dim = d):
  *   0..d-1     x_k           walk location
- *   d..2d-1    nu_k          drawn direction (after reflection)
+ *   d..2d-1    nu_k          drawn direction (after reflection, if on;
+ *                            wasted draws write no record)
  *   2d..3d-1   n_k           unit normal on the walk's side if x_k is on the
  *                            Neumann boundary, else 0
  *   3d         p_sample      MIS pdf of nu_k at draw time
@@ -233,6 +239,16 @@ int wost_guide_create(const wost_guide_config* cfg, wost_guide** out);
  * row-major [in][out] (first layer in = L*F, hidden width 64, last out =
  * K*(dim+2)+1; per lobe (mu'_1..mu'_dim, kappa', lambda'), then c'). */
 int64_t wost_guide_param_count(const wost_guide* g);
+/* Sample reflection at Neumann points (Sec. 4.3), default 1.  With 0, the
+ * guided branch of a draw at a Neumann point keeps the plain mixture: a draw
+ * with nu . n <= 0 is wasted, and p_g on the valid half is the mixture itself
+ * (the "without reflection" variant of the ablation in Sec. 6).  The setting
+ * is read by wost_guide_sample, by the training loss (which p_g a Neumann
+ * record is scored with) and checked against wost_problem.reflect by
+ * wost_solve.  reflect must be 0 or 1, else WOST_EINVAL. */
+int wost_guide_set_reflect(wost_guide* g, int32_t reflect);
+/* The current setting (0 or 1), -1 for a NULL handle. */
+int32_t wost_guide_get_reflect(const wost_guide* g);
 /* Bytes of the half-precision shadow used by inference (grid entries in the
  * same order, MLP weights re-arranged into MFMA operand fragments). */
 int64_t wost_guide_shadow_bytes(const wost_guide* g);
@@ -254,9 +270,11 @@ int wost_guide_infer(const wost_guide* g, const float* pts, int64_t n, float* ou
  * of walk (i, walk_index) with Philox key `seed`: pts device [n][dim];
  * normals device [n][dim] or NULL -- a nonzero row marks a point on the
  * Neumann boundary with that unit normal on the walk's side (draws are then
- * reflected into the valid half, Sec. 4.3); sampling is a guided
- * WOST_SAMPLING_* mode.  Outputs: out_nu [n][dim], out_pdf [n] = the MIS pdf
- * c p_g + (1 - c) p_u of the returned direction (Sec. 4.4). */
+ * reflected into the valid half, Sec. 4.3, if the guide's reflection setting
+ * is on); sampling is a guided WOST_SAMPLING_* mode.  Outputs: out_nu
+ * [n][dim], out_pdf [n] = the MIS pdf c p_g + (1 - c) p_u of the returned
+ * direction (Sec. 4.4), or -1 for a wasted draw (reflection off: a guided
+ * draw with nu . n <= 0, returned unreflected). */
 int wost_guide_sample(const wost_guide* g, int32_t sampling, float c_fixed, const float* pts,
                       const float* normals, int64_t n, uint64_t seed, uint32_t walk_index, float* out_nu,
                       float* out_pdf, void* stream);
@@ -269,7 +287,8 @@ void wost_guide_free(wost_guide* g);
  *     w = p_t / p_sample,
  * whose gradient w.r.t. Theta is the one-sample KL gradient of Sec. 4.2
  * (equation "one_sample_kld", with p_g the reflected mixture on Neumann
- * points, Sec. 4.3) and w.r.t. c the selection-probability gradient of
+ * points, Sec. 4.3, or the plain mixture if the guide's reflection setting is
+ * off) and w.r.t. c the selection-probability gradient of
  * Sec. 4.4 (equation "one_sample_sp"); sg is stop-gradient.  Records are
  * rows [begin, begin + count) of a wost_records buffer. */
 typedef struct {

@@ -74,6 +74,8 @@ SIGNATURES = {
     "wost_set_cost_counters": (_I, [_P]),
     "wost_guide_create": (_I, [C.POINTER(wost_guide_config), C.POINTER(_P)]),
     "wost_guide_param_count": (_I64, [_P]),
+    "wost_guide_set_reflect": (_I, [_P, C.c_int32]),
+    "wost_guide_get_reflect": (_I, [_P]),
     "wost_guide_shadow_bytes": (_I64, [_P]),
     "wost_guide_bind": (_I, [_P, _P, _P, _P, _P, _P]),
     "wost_guide_init": (_I, [_P, _U64, _P]),

@@ -155,6 +155,16 @@ extern "C" int wost_guide_create(const wost_guide_config* c, wost_guide** out)
 
 extern "C" int64_t wost_guide_param_count(const wost_guide* g) { return g ? g->n_params : -1; }
 
+extern "C" int wost_guide_set_reflect(wost_guide* g, int32_t reflect)
+{
+    if (!g) { set_error("wost_guide_set_reflect: NULL handle"); return WOST_EINVAL; }
+    if (reflect != 0 && reflect != 1) { set_error("wost_guide_set_reflect: reflect must be 0 or 1"); return WOST_EINVAL; }
+    g->dev.reflect = reflect;
+    return WOST_OK;
+}
+
+extern "C" int32_t wost_guide_get_reflect(const wost_guide* g) { return g ? g->dev.reflect : -1; }
+
 extern "C" int64_t wost_guide_shadow_bytes(const wost_guide* g)
 {
     return g ? 2 * (g->frag_base + g->n_frag_halves) : -1;

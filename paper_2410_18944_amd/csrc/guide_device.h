@@ -344,7 +344,10 @@ __device__ __forceinline__ void onb(const float* n, float* t1, float* t2)
 // One MIS draw (Sec. 4.4): with probability c a lobe ~ lambda and a vMF
 // sample from it, else uniform; invalid draws on a Neumann boundary are
 // reflected about the tangent plane (Sec. 4.3).  Returns nu and the MIS pdf
-// c p_g(nu) + (1 - c) p_u(nu) of the direction actually used.
+// c p_g(nu) + (1 - c) p_u(nu) of the direction actually used.  With
+// reflection off (g.reflect = 0, the ablation of Sec. 6) p_g on a Neumann
+// point is the plain mixture on the valid half, and a guided draw into the
+// wall (nu . n <= 0) returns *pmis = -1: its recursive term is zero.
 template <int D>
 __device__ __forceinline__ void guided_draw(const GuideDev& g, const float* y, const Stream& rs, uint32_t step,
                                             const uint4& wd, bool onN, const float* nin, float* nu, float* pmis)
@@ -396,8 +399,13 @@ __device__ __forceinline__ void guided_draw(const GuideDev& g, const float* y, c
     // reflection into the valid hemisphere on a Neumann boundary; the guided
     // density of the used direction then sums the lobes at nu and at its mirror
     float nr[D];
+    const bool mirror = onN && g.reflect != 0;
     if (onN) {
         float cn = dot<D>(nu, nin);
+        if (guided && !mirror && cn <= 0.f) {
+            *pmis = -1.f;
+            return;
+        }
         if (cn < 0.f) {
 #pragma unroll
             for (int i = 0; i < D; ++i) nu[i] = fmaf(-2.f * cn, nin[i], nu[i]);
@@ -412,7 +420,7 @@ __device__ __forceinline__ void guided_draw(const GuideDev& g, const float* y, c
         const float lam = expf(lobe_logit<D>(y, i) - lmax) * il;
         const float ln = vmf_lognorm<D>(L.kappa);
         pg = fmaf(lam, expf(fmaf(L.kappa, dot<D>(L.mu, nu) - 1.f, ln)), pg);
-        if (onN) pr = fmaf(lam, expf(fmaf(L.kappa, dot<D>(L.mu, nr) - 1.f, ln)), pr);
+        if (mirror) pr = fmaf(lam, expf(fmaf(L.kappa, dot<D>(L.mu, nr) - 1.f, ln)), pr);
     }
     if (onN) *pmis = c * (pg + pr) + (1.f - c) * (2.f / area);
     else *pmis = c * pg + (1.f - c) * (1.f / area);

@@ -82,9 +82,11 @@ __device__ __forceinline__ float softplus(float z) { return fmaxf(z, 0.f) + log1
 
 // Loss of one record and (optionally, in place) its gradient w.r.t. the raw
 // outputs y (row in LDS; padded entries untouched).  dscale multiplies dy.
+// On a Neumann record p_g is the reflected mixture (Sec. 4.3) when mirror is
+// set, else the plain mixture (reflection off).
 template <int D>
-__device__ float record_loss_grad(float* y, int K, const float* nu, const float* n, bool onN, float ps, float pt,
-                                  float e, bool want_grad, float dscale)
+__device__ float record_loss_grad(float* y, int K, const float* nu, const float* n, bool onN, bool mirror, float ps,
+                                  float pt, float e, bool want_grad, float dscale)
 {
     const float area = D == 2 ? 2.f * kPi : 4.f * kPi;
     float nr[D];
@@ -115,7 +117,7 @@ __device__ float record_loss_grad(float* y, int K, const float* nu, const float*
         float mt = fmaxf(m, t1);
         s = s * expf(m - mt) + expf(t1 - mt);
         m = mt;
-        if (onN) {
+        if (mirror) {
             const float t2 = fmaf(k, dot<D>(mu, nr) - 1.f, base);
             mt = fmaxf(m, t2);
             s = s * expf(m - mt) + expf(t2 - mt);
@@ -157,7 +159,7 @@ __device__ float record_loss_grad(float* y, int K, const float* nu, const float*
         const float c1 = dot<D>(mu, nu);
         const float g1 = expf(fmaf(k, c1 - 1.f, base) - log_pg);
         float c2 = 0.f, g2 = 0.f;
-        if (onN) {
+        if (mirror) {
             c2 = dot<D>(mu, nr);
             g2 = expf(fmaf(k, c2 - 1.f, base) - log_pg);
         }
@@ -168,7 +170,7 @@ __device__ float record_loss_grad(float* y, int K, const float* nu, const float*
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             float v = g1 * (nu[d] - c1 * mu[d]);
-            if (onN) v += g2 * (nr[d] - c2 * mu[d]);
+            if (mirror) v += g2 * (nr[d] - c2 * mu[d]);
             dmu[d] = v * k * inv;
         }
 #pragma unroll
@@ -308,7 +310,8 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
         // ---------------- per-record loss and output gradient (lane = record)
         float* yrow = s_y + lane * ystride;
         const float up = valid ? (a.dloss ? a.dloss[i] : 1.f) * a.scale : 0.f;
-        const float loss = record_loss_grad<D>(yrow, K, nu, nn, onN, ps, pt, a.e_mis, a.backward != 0, up);
+        const float loss = record_loss_grad<D>(yrow, K, nu, nn, onN, onN && g.reflect != 0, ps, pt, a.e_mis,
+                                               a.backward != 0, up);
         if (valid) {
             if (a.loss_out) a.loss_out[i] = loss;
             loss_acc += loss;

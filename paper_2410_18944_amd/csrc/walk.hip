@@ -323,50 +323,59 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                 const float r = pv.f(F::R, g), th = pv.f(F::TH, g), w = pv.f(F::W, g);
                 const int hp = pv.i(F::HIT, g);
                 acc = fmaf(T, pv.f(F::CON, g), acc);
-#pragma unroll
-                for (int i = 0; i < D; ++i) { rec_x[i] = x[i]; rec_nin[i] = onN ? nin[i] : 0.f; rec_nu[i] = nu[i]; }
-                float xo[D];
-#pragma unroll
-                for (int i = 0; i < D; ++i) xo[i] = onN ? fmaf(G.tau, nin[i], x[i]) : x[i];
-                if (hp >= 0) {
-                    // the walk's side of a Neumann primitive is the domain, so
-                    // its normal toward the walk is -n_out (a first hit seen
-                    // from inside is always an exit, nu . n_out > 0)
-                    const float4 ex = G.neu.pextra[hp];
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        x[i] = fmaf(th, nu[i], xo[i]);
-                        nin[i] = -(i == 0 ? ex.x : (i == 1 ? ex.y : ex.z));
-                    }
-                    onp = hp;
+                // a guided draw wasted into the wall (reflection off): this
+                // star's terms count, its recursive term is zero, the walk ends
+                const bool wasted = GUIDED && pv.f(F::PMIS, g) < 0.f;
+                if (wasted) {
+                    pv.f(F::ACC, g) = acc;
+                    pv.i(F::K, g) = k + 1;
+                    stt = ST_DONE;
                 } else {
-                    // the segment from the ray's origin to this point crosses
-                    // no boundary, so the walker stays inside; stepping from
-                    // x itself could leave the domain by up to tau along a
-                    // grazing ray
 #pragma unroll
-                    for (int i = 0; i < D; ++i) x[i] = fmaf(r, nu[i], xo[i]);
-                    onp = -1;
-                }
-                T *= w;
-                ++k;
-                stt = ST_ACTIVE;
-                // Russian roulette for the next star (played with that step's word)
-                if (k >= P.rr_start) {
-                    const uint4 wr = walk_stream(P, wid).block((uint32_t)k, kBlkNeu);
-                    if (u01(wr.w) >= P.rr_q) { stt = ST_DONE; ++n_rr; }
-                    else T /= P.rr_q;
-                }
+                    for (int i = 0; i < D; ++i) { rec_x[i] = x[i]; rec_nin[i] = onN ? nin[i] : 0.f; rec_nu[i] = nu[i]; }
+                    float xo[D];
 #pragma unroll
-                for (int i = 0; i < D; ++i) { pv.f(F::X + i, g) = x[i]; pv.f(F::NIN + i, g) = nin[i]; }
-                pv.i(F::ONP, g) = onp;
-                pv.f(F::T, g) = T;
-                pv.f(F::ACC, g) = acc;
-                pv.i(F::K, g) = k;
-                rec_pmis = pv.f(F::PMIS, g);
-                rec_prefix = acc;
-                rec_tnext = T;
-                do_rec = GUIDED && P.rec.data != nullptr;
+                    for (int i = 0; i < D; ++i) xo[i] = onN ? fmaf(G.tau, nin[i], x[i]) : x[i];
+                    if (hp >= 0) {
+                        // the walk's side of a Neumann primitive is the domain, so
+                        // its normal toward the walk is -n_out (a first hit seen
+                        // from inside is always an exit, nu . n_out > 0)
+                        const float4 ex = G.neu.pextra[hp];
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            x[i] = fmaf(th, nu[i], xo[i]);
+                            nin[i] = -(i == 0 ? ex.x : (i == 1 ? ex.y : ex.z));
+                        }
+                        onp = hp;
+                    } else {
+                        // the segment from the ray's origin to this point crosses
+                        // no boundary, so the walker stays inside; stepping from
+                        // x itself could leave the domain by up to tau along a
+                        // grazing ray
+#pragma unroll
+                        for (int i = 0; i < D; ++i) x[i] = fmaf(r, nu[i], xo[i]);
+                        onp = -1;
+                    }
+                    T *= w;
+                    ++k;
+                    stt = ST_ACTIVE;
+                    // Russian roulette for the next star (played with that step's word)
+                    if (k >= P.rr_start) {
+                        const uint4 wr = walk_stream(P, wid).block((uint32_t)k, kBlkNeu);
+                        if (u01(wr.w) >= P.rr_q) { stt = ST_DONE; ++n_rr; }
+                        else T /= P.rr_q;
+                    }
+#pragma unroll
+                    for (int i = 0; i < D; ++i) { pv.f(F::X + i, g) = x[i]; pv.f(F::NIN + i, g) = nin[i]; }
+                    pv.i(F::ONP, g) = onp;
+                    pv.f(F::T, g) = T;
+                    pv.f(F::ACC, g) = acc;
+                    pv.i(F::K, g) = k;
+                    rec_pmis = pv.f(F::PMIS, g);
+                    rec_prefix = acc;
+                    rec_tnext = T;
+                    do_rec = GUIDED && P.rec.data != nullptr;
+                }
             }
             if (stt == ST_DONE) {
                 if (!do_rec) wid = pv.wid(g);
@@ -566,8 +575,11 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                     const Stream rs = walk_stream(P, pv.wid(g));
                     const uint4 wd = rs.block((uint32_t)k, kBlkDir);
                     guided_draw<D>(P.guide, s_out + lane * out_stride, rs, (uint32_t)k, wd, onN, nin, nu, &pmis);
-                    float w = (onN ? 2.f : 1.f) / (area * pmis);
-                    if (!(w >= 0.f && w < INFINITY)) { ++n_bad; w = 0.f; }
+                    float w = 0.f;
+                    if (pmis >= 0.f) {
+                        w = (onN ? 2.f : 1.f) / (area * pmis);
+                        if (!(w >= 0.f && w < INFINITY)) { ++n_bad; w = 0.f; }
+                    }
 #pragma unroll
                     for (int i = 0; i < D; ++i) pv.f(F::NU + i, g) = nu[i];
                     pv.f(F::W, g) = w;
@@ -1096,18 +1108,19 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     P.slot_steps = walk_steps;
     P.counters = (unsigned long long*)dev_counters;
     P.cost = g_cost;
-    if (guided && !pb->reflect) {
-        // guided draws into the wall are always reflected (Sec. 4.3); the
-        // variant that wastes them is not implemented
-        set_error("wost_solve: guided sampling needs reflect = 1");
-        return WOST_EUNSUPPORTED;
+    if (guided && guide && (pb->reflect != 0) != (guide->dev.reflect != 0)) {
+        // the training loss reads the guide's setting, so a solve that draws
+        // otherwise would train against another density than it sampled
+        set_error("wost_solve: problem.reflect = %d but the guide's reflection setting is %d "
+                  "(wost_guide_set_reflect)", pb->reflect != 0, guide->dev.reflect != 0);
+        return WOST_EINVAL;
     }
     if (guided) {
         int rc = guide_prepare(guide, dim, P.guide);
         if (rc != WOST_OK) return rc;
         P.guide.sampling = pb->sampling;
         P.guide.c_fixed = pb->c_fixed;
-        P.guide.reflect = pb->reflect;
+        P.guide.reflect = pb->reflect != 0;
     }
     if (rec) {
         if (!guided) { set_error("wost_solve: training records need a guided sampling mode"); return WOST_EINVAL; }

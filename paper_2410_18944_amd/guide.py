@@ -79,6 +79,16 @@ class Guide:
             lib.wost_guide_free(self.h)
             self.h = None
 
+    @property
+    def reflect(self) -> bool:
+        """Sample reflection at Neumann points (Sec. 4.3); False selects the
+        variant without it (guided draws into the wall are wasted)."""
+        return bool(L.load().wost_guide_get_reflect(self.h))
+
+    @reflect.setter
+    def reflect(self, on):
+        L.check(L.load().wost_guide_set_reflect(self.h, 1 if on else 0), "wost_guide_set_reflect")
+
     def set_params(self, flat):
         """Overwrite the fp32 master parameters and refresh the fp16 shadow."""
         self.master.copy_(torch.as_tensor(flat, dtype=torch.float32))

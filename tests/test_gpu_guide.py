@@ -115,13 +115,17 @@ def _philox_blocks(O, n, j, step, blocks, seed):
     return (w >> 8).astype(np.float64) * 2.0 ** -24
 
 
-@pytest.mark.parametrize("dim,mode,K", [(d, m, 8) for d in (2, 3) for m in ("mis_learned", "mis_fixed", "guided_only")]
-                         + [(2, "mis_learned", 4), (2, "mis_learned", 16)])
-def test_guide_sample_matches_reference_on_same_words(W, O, dim, mode, K):
+@pytest.mark.parametrize("dim,mode,K,reflected",
+                         [(d, m, 8, True) for d in (2, 3) for m in ("mis_learned", "mis_fixed", "guided_only")]
+                         + [(2, "mis_learned", 4, True), (2, "mis_learned", 16, True)]
+                         + [(2, "mis_learned", 8, False), (3, "mis_learned", 8, False), (2, "guided_only", 8, False)])
+def test_guide_sample_matches_reference_on_same_words(W, O, dim, mode, K, reflected):
     from oracle import guide_ref as G
     s = _scene_2d() if dim == 2 else _scene_3d()
     kw = dict(K=K) if dim == 2 else dict(log2_table=14, K=K)
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=10 + dim, **kw)
+    g.reflect = reflected
+    assert g.reflect == reflected
     rng = np.random.default_rng(8 + dim)
     n = 2048
     pts = np.asarray(rng.uniform(rcfg.lo, rcfg.hi, (n, dim)), np.float32).astype(np.float64)
@@ -130,7 +134,7 @@ def test_guide_sample_matches_reference_on_same_words(W, O, dim, mode, K):
     nrm[: n // 2] = 0.0                                  # first half interior, second half on a wall
     nrm = np.asarray(nrm, np.float32).astype(np.float64)
     seed, j = 1234567, 5
-    say("guide sample", dim, mode)
+    say("guide sample", dim, mode, "reflected" if reflected else "not reflected")
     nu, pdf = g.sample(_t(pts), _t(nrm), sampling=mode, c_fixed=0.35, seed=seed, walk_index=j)
     y = g.infer(_t(pts)).double().cpu().numpy()
     nu = nu.double().cpu().numpy()
@@ -142,22 +146,31 @@ def test_guide_sample_matches_reference_on_same_words(W, O, dim, mode, K):
         c = np.ones(n)
     words = _philox_blocks(O, n, j, 0, list(range(0, 4)) + list(range(4, 4 + 16)), seed)
     agree = 0
+    wasted = 0
     pdf_err = []
     for i in range(n):
         onN = bool(np.any(nrm[i] != 0))
         b0 = words[i, 0]
         b3 = words[i, 3]
         bf = [tuple(words[i, 4 + t, :3]) for t in range(16)]
-        nu_r, p_r, _ = G.sample_direction(dim, mu[i], kappa[i], lam[i], c[i], b0, b3, bf, onN, nrm[i] if onN else None)
-        agree += np.linalg.norm(nu_r - nu[i]) < 2e-3
+        nu_r, p_r, _ = G.sample_direction(dim, mu[i], kappa[i], lam[i], c[i], b0, b3, bf, onN, nrm[i] if onN else None,
+                                          reflected)
+        agree += np.linalg.norm(nu_r - nu[i]) < 2e-3 and (pdf[i] < 0) == (p_r == 0.0)
+        if pdf[i] < 0:
+            # a wasted draw: only without reflection, only into the wall
+            assert onN and not reflected and np.dot(nu[i], nrm[i]) <= 1e-6
+            wasted += 1
+            continue
         # pdf of the GPU's own direction under the same mapped parameters
-        p_at = G.mis_pdf(nu[i], mu[i], kappa[i], lam[i], c[i], dim, onN, nrm[i] if onN else None)
+        p_at = G.mis_pdf(nu[i], mu[i], kappa[i], lam[i], c[i], dim, onN, nrm[i] if onN else None, reflected)
         pdf_err.append(abs(pdf[i] - p_at) / p_at)
         if onN:
             assert np.dot(nu[i], nrm[i]) >= -1e-6
     pdf_err = np.asarray(pdf_err)
-    say("sample agree %.4f, pdf rel err p99 %.2e max %.2e" % (agree / n, np.percentile(pdf_err, 99), pdf_err.max()))
+    say("sample agree %.4f, wasted %d, pdf rel err p99 %.2e max %.2e"
+        % (agree / n, wasted, np.percentile(pdf_err, 99), pdf_err.max()))
     assert agree / n > 0.99
+    assert (wasted > 0) == (not reflected)
     assert np.percentile(pdf_err, 99) < 1e-4 and pdf_err.max() < 1e-2
     np.testing.assert_allclose(np.linalg.norm(nu, axis=1), 1.0, atol=1e-5)
 
@@ -208,6 +221,7 @@ def test_guided_c2_unbiased_with_reflection(W):
     geom = W.Geometry.from_scene(s)
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=41)
     say("guided C2", len(pts))
+    # the problem's reflection flag must match the guide's setting
     with pytest.raises(RuntimeError, match="reflect"):
         _solve(W, s, geom, W.Problem.from_scene(s, sampling="mis_learned", reflect=False), pts[:8], 4, guide=g)
     r = _solve(W, s, geom, W.Problem.from_scene(s, sampling="mis_learned"), pts, 512, guide=g)
@@ -215,6 +229,34 @@ def test_guided_c2_unbiased_with_reflection(W):
     u = _solve(W, s, geom, W.Problem.from_scene(s), pts, 512)
     z = two_sample_z(r["mean"], r["se"], u["mean"], u["se"])
     assert abs(z.mean()) < 5 / np.sqrt(len(z)) and np.mean(np.abs(z) > 3) < 0.01
+
+
+def test_guided_c2_unbiased_without_reflection(W):
+    """Reflection off (the ablation of the reflection step): guided draws into
+    the wall end the walk with a zero recursive term, and the estimate must
+    stay unbiased; records are written only for directions actually used."""
+    s = _scene_2d()
+    pts = s.points[::11]
+    geom = W.Geometry.from_scene(s)
+    g, cfg, rcfg, p16 = _guide_setup(W, s, seed=42)
+    g.reflect = False
+    say("guided C2 without reflection", len(pts))
+    with pytest.raises(RuntimeError, match="reflect"):
+        _solve(W, s, geom, W.Problem.from_scene(s, sampling="mis_learned"), pts[:8], 4, guide=g)
+    pb = W.Problem.from_scene(s, sampling="mis_learned", reflect=False)
+    r = _solve(W, s, geom, pb, pts, 512, guide=g)
+    zscore_check(r["mean"], r["se"], exact_solution(s, pts), r["n"], label="guided C2 no reflection")
+    assert r["stats"]["nonfinite"] == 0
+    rec = W.Records(2, capacity=256 * 16 * 256)
+    r = _solve(W, s, geom, pb, pts[:256], 16, guide=g, records=rec)
+    nrec = rec.n()
+    assert nrec == r["stats"]["records"] and r["stats"]["records_dropped"] == 0
+    F = {k: v.cpu().numpy() for k, v in rec.fields(nrec).items()}
+    on = np.any(F["n"] != 0, axis=1)
+    assert on.any()
+    # every recorded direction at a Neumann point lies in the valid half
+    assert np.all(np.sum(F["nu"][on] * F["n"][on], axis=1) >= -1e-6)
+    assert np.all(F["p_sample"] > 0)
 
 
 def test_guided_3d_sphere_unbiased(W):
@@ -296,13 +338,15 @@ def _synthetic_records(W, rcfg, n, rng, dim):
     return rec, (f64(x), f64(nu), f64(nr), on, f64(ps), f64(pt))
 
 
-@pytest.mark.parametrize("dim,K", [(2, 8), (3, 8), (2, 4), (2, 16)])
-def test_loss_and_backward_match_fp64_reference(W, dim, K):
+@pytest.mark.parametrize("dim,K,reflected", [(2, 8, True), (3, 8, True), (2, 4, True), (2, 16, True),
+                                             (2, 8, False), (3, 8, False)])
+def test_loss_and_backward_match_fp64_reference(W, dim, K, reflected):
     from oracle import guide_ref as G
     s = _scene_2d() if dim == 2 else _scene_3d()
     kw = dict(K=K) if dim == 2 else dict(log2_table=14, K=K)
     # MLP weights at 0.6x He scale keep kappa' in the range a trained guide uses
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=70 + dim, mlp_gain=0.6, **kw)
+    g.reflect = reflected
     rng = np.random.default_rng(71 + dim)
     n = 3000
     rec, batch = _synthetic_records(W, rcfg, n, rng, dim)
@@ -310,7 +354,7 @@ def test_loss_and_backward_match_fp64_reference(W, dim, K):
     loss = g.loss_fwd(rec).double().cpu().numpy()
     with torch.no_grad():
         y = G.forward(rcfg, p16, batch[0], round_inputs=True)
-        ref_loss = G.loss_per_sample(rcfg, y, *batch[1:]).numpy()
+        ref_loss = G.loss_per_sample(rcfg, y, *batch[1:], reflected=reflected).numpy()
     lerr = np.abs(loss - ref_loss) / (np.abs(ref_loss) + np.mean(np.abs(ref_loss)))
     say("loss rel err max %.2e" % lerr.max())
     assert np.percentile(lerr, 99) < 2e-3
@@ -327,7 +371,7 @@ def test_loss_and_backward_match_fp64_reference(W, dim, K):
     p = torch.tensor(p16, dtype=torch.float64, requires_grad=True)
     y_ref = G.forward(rcfg, p, batch[0], round_inputs=True)
     y_at = y_ref + (y_gpu - y_ref).detach()
-    G.loss_per_sample(rcfg, y_at, *batch[1:]).mean().backward()
+    G.loss_per_sample(rcfg, y_at, *batch[1:], reflected=reflected).mean().backward()
     ref_grad = p.grad.numpy()
     rel = np.linalg.norm(grad - ref_grad) / np.linalg.norm(ref_grad)
     ng = rcfg.n_grid_params
