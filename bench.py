@@ -52,7 +52,7 @@ def bytes_per_step(cost, dim):
     return sum(c["nodes_per_step"] * nb[q] + c["prims_per_step"] * kinds[q] for q, c in cost.items())
 
 
-WALK_SOURCES = ["walk.hip", "geom_device.h", "guide_device.h", "walk_common.h", "wost_internal.h", "../build.py"]
+WALK_SOURCES = ["walk.hip", "walk_state.h", "geom_device.h", "guide_device.h", "walk_common.h", "wost_internal.h", "../build.py"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_kernel2g_c3_guided_traffic.md")
 
 
@@ -209,6 +209,40 @@ def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2
         one("%d Adam steps per batch" % steps, steps=steps)
 
 
+def run_engine_ab(W, online_solve, OnlineSchedule, s, geom, pts, u, args, reps=2):
+    """The persistent fused walk kernel against the multi-kernel wavefront
+    solver (one kernel per stage over compacted walk queues, the paper's own
+    GPU organisation) on the bench workload: uniform and guided online
+    solves, same seeds; prints one JSON line per engine."""
+    import torch
+
+    for engine in ("persistent", "wavefront"):
+        rows = []
+        for r in range(reps):
+            seed = 700 + r
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[0].record()
+            acc_u = W.solve(geom, W.Problem.from_scene(s), pts, args.wpp, seed=18944 + seed, engine=engine)
+            ev[1].record()
+            g = W.Guide(W.GuideConfig.for_scene(s), seed=seed)
+            sched = OnlineSchedule(batch_wpp=args.batch_wpp, train_until_wpp=args.train_until)
+            ev[2].record()
+            acc_g, info = online_solve(geom, W.Problem.from_scene(s, sampling="mis_learned"), pts, args.wpp, g, sched,
+                                       seed=18944 + seed, engine=engine)
+            ev[3].record()
+            torch.cuda.synchronize()
+            su, sg = acc_u.stats(), acc_g.stats()
+            t_u, t_g = ev[0].elapsed_time(ev[1]) * 1e-3, ev[2].elapsed_time(ev[3]) * 1e-3
+            rows.append(dict(uniform_s=t_u, uniform_steps_per_s=su["steps"] / t_u,
+                             uniform_rel_mse=rel_mse(acc_u.estimates()[0].cpu().numpy(), u),
+                             guided_s=t_g, guided_walk_s=info["phase_s"]["walk"],
+                             guided_steps_per_s=sg["steps"] / t_g,
+                             guided_rel_mse=rel_mse(acc_g.estimates()[0].cpu().numpy(), u)))
+        out = {k: float(np.mean([r[k] for r in rows])) for k in rows[0]}
+        out.update(engine=engine, reps=reps, wpp=args.wpp, points=int(pts.shape[0]))
+        print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,6 +257,9 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     ap.add_argument("--guide-mlp", action="store_true",
                     help="only time the standalone guide MLP (Adam step at 2^18, inference at 2^20) and exit")
+    ap.add_argument("--engine-ab", action="store_true",
+                    help="instead of the bench line: the persistent walk kernel against the multi-kernel "
+                         "wavefront solver on the bench workload")
     ap.add_argument("--ablations", action="store_true",
                     help="instead of the bench line: sampling-mode ablations (K, selection c, reflection) and the "
                          "training-schedule sweep on the same workload, one JSON line per configuration")
@@ -281,6 +318,9 @@ def main():
     torch.cuda.synchronize()
     if args.ablations:
         run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args)
+        return
+    if args.engine_ab:
+        run_engine_ab(W, online_solve, OnlineSchedule, s, geom, pts, u, args)
         return
 
     # ---- timed region: K guided solves

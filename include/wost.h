@@ -215,6 +215,26 @@ int wost_solve(const wost_geom* geom, const wost_problem* problem, const float* 
                float* walk_value, int32_t* walk_steps, const wost_records* rec, void* workspace,
                int64_t ws_bytes, uint64_t* dev_counters, void* stream);
 
+/* The same solve organised as the paper's GPU system (Sec. 5.1; Sec. 5.2
+ * "System Integration"): the state of every walk of the call lives in the
+ * workspace, and each step of all live walks is a sequence of kernels, one
+ * per stage (closest Dirichlet point, silhouette and radius, guided direction
+ * batched over all stepping walks, Neumann sample and its visibility, source
+ * point and its visibility, first hit, update), over queues of walk ids that
+ * each stage compacts for the next.  Arguments, outputs and errors as
+ * wost_solve; walks use the same random words and traversal code, so per-walk
+ * values and step counts agree with wost_solve's.  Unlike wost_solve it
+ * waits on `stream`: the host reads the live-walk count back every eight
+ * steps and stops when it reaches zero.  Traversal-cost counters
+ * (wost_set_cost_counters) are not supported (WOST_EUNSUPPORTED).  Kept as
+ * the baseline the persistent kernel is measured against. */
+int64_t wost_solve_wavefront_workspace_bytes(const wost_geom* geom, int64_t n_points, int32_t wpp);
+int wost_solve_wavefront(const wost_geom* geom, const wost_problem* problem, const float* pts, int64_t n_points,
+                         int32_t wpp, uint64_t seed, uint64_t walk_offset, const wost_guide* guide, double* sum,
+                         double* sum_sq, int64_t* count, float* walk_value, int32_t* walk_steps,
+                         const wost_records* rec, void* workspace, int64_t ws_bytes, uint64_t* dev_counters,
+                         void* stream);
+
 /* ------------------------------------------------------------ guide
  * The neural field of Sec. 5.2: a multi-resolution grid (hashed where a
  * level's dense lattice exceeds the table) followed by a bias-free ReLU MLP

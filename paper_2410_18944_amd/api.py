@@ -187,24 +187,34 @@ class Accumulator:
         return {k: int(v) for k, v in zip(COUNTER_NAMES, c)}
 
 
+ENGINES = {"persistent": ("wost_solve", "wost_solve_workspace_bytes"),
+           "wavefront": ("wost_solve_wavefront", "wost_solve_wavefront_workspace_bytes")}
+
+
 def solve(geom, problem, pts, wpp, seed=18944, walk_offset=0, guide=None, acc=None, walk_value=None,
-          walk_steps=None, records=None, workspace=None):
-    """Launch wost_solve on the current stream; returns the Accumulator."""
+          walk_steps=None, records=None, workspace=None, engine="persistent"):
+    """Launch a solve on the current stream; returns the Accumulator.
+    ``engine``: "persistent" (wost_solve, the fused persistent kernel) or
+    "wavefront" (wost_solve_wavefront, one kernel per stage; it waits for
+    the stream while it runs)."""
     lib = L.load()
+    if engine not in ENGINES:
+        raise ValueError("engine must be one of %s" % sorted(ENGINES))
+    fn, ws_fn = ENGINES[engine]
     pts = pts.contiguous()
     n = pts.shape[0]
     if acc is None:
         acc = Accumulator(n, pts.device)
-    need = max(int(lib.wost_solve_workspace_bytes(geom.h, n, int(wpp))), 256)
+    need = max(int(getattr(lib, ws_fn)(geom.h, n, int(wpp))), 256)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=pts.device)
     pb, keep = problem.to_c()
     rec = records.to_c() if records is not None else None
-    L.check(lib.wost_solve(geom.h, C.byref(pb), _ptr(pts), n, int(wpp), int(seed), int(walk_offset),
-                           guide.h if guide is not None else None, _ptr(acc.sum), _ptr(acc.sum_sq),
-                           _ptr(acc.count), _ptr(walk_value), _ptr(walk_steps),
-                           C.byref(rec) if rec is not None else None, _ptr(workspace), workspace.numel(),
-                           _ptr(acc.counters), _stream()), "wost_solve")
+    L.check(getattr(lib, fn)(geom.h, C.byref(pb), _ptr(pts), n, int(wpp), int(seed), int(walk_offset),
+                             guide.h if guide is not None else None, _ptr(acc.sum), _ptr(acc.sum_sq),
+                             _ptr(acc.count), _ptr(walk_value), _ptr(walk_steps),
+                             C.byref(rec) if rec is not None else None, _ptr(workspace), workspace.numel(),
+                             _ptr(acc.counters), _stream()), fn)
     del keep
     return acc
 

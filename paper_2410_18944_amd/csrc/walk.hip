@@ -18,76 +18,9 @@
 #include "guide_device.h"
 #include "guide_internal.h"
 #include "walk_common.h"
+#include "walk_state.h"
 
 namespace wost {
-
-struct WalkParams {
-    DevGeom geom;
-    FieldDev g, h, f;
-    float eps, r_min, rr_q;
-    int32_t max_steps, rr_start;
-    int32_t sampling;
-    float c_fixed;
-    int32_t reflect;
-    const float* pts;
-    int64_t n_points;
-    int32_t wpp;
-    uint32_t key0, key1;
-    uint64_t walk_offset;
-    uint64_t n_walks;
-    float* slot_value;
-    int32_t* slot_steps;
-    unsigned long long* work;       // global walk counter
-    uint64_t chunk;                 // walks a wave reserves per atomic
-    unsigned long long* counters;   // 8 stats
-    unsigned long long* cost;       // 12 traversal counters (statistics variant only)
-    GuideDev guide;
-    RecDev rec;
-    uint32_t* pool;                 // walk pools: PoolField<D>::WORDS arrays of pool_total words
-    int64_t pool_total;             // slots over all waves (grid * pool_n)
-    int32_t pool_n;                 // slots per wave (multiple of 64)
-    int32_t* lists;                 // 4 work lists of pool_n entries per wave
-    int32_t refill_batch;           // finished lanes that wait for a joint refill
-};
-
-__device__ __forceinline__ uint32_t lane_prefix(uint64_t mask)
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
-
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t w = __shfl_xor(v, o);
-        v = w > v ? w : v;
-    }
-    return v;
-}
-
-__device__ __forceinline__ float wave_sum_f(float v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum_i(int v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)v, o), hi = __shfl_xor((uint32_t)(v >> 32), o);
-        v += ((unsigned long long)hi << 32) | lo;
-    }
-    return v;
-}
 
 // LDS bytes of one walk workgroup: the traversal stack and the guide's output
 // transpose are used in different phases of a step and share the space.  A
@@ -111,61 +44,6 @@ static inline size_t walk_lds_bytes(bool guided, int stack_entries, int out_stri
 // update.  Inside a traversal phase a lane whose query has finished takes the
 // next walk of that phase's list at once, so the wave does not wait for its
 // slowest lane; lanes of a phase all run the same query code.
-
-// ST_VIS: a stepping walk whose Neumann sample waits for its visibility ray
-enum : int { ST_EMPTY = 0, ST_ACTIVE = 1, ST_STEP = 2, ST_DONE = 3, ST_VIS = 4 };
-
-template <int D>
-struct PoolField {
-    static constexpr int X = 0, NIN = D, NU = 2 * D, Z = 3 * D, Y = 4 * D;
-    static constexpr int T = 5 * D, ACC = T + 1, DD = T + 2, R = T + 3, W = T + 4, PMIS = T + 5, CON = T + 6,
-                         NVAL = T + 7, SVAL = T + 8, TH = T + 9, K = T + 10, ONP = T + 11, HIT = T + 12,
-                         STAT = T + 13, WLO = T + 14, WHI = T + 15;
-    static constexpr int WORDS = T + 16;
-};
-
-// Field-major storage (field f of global slot g at pool[f * total + g]):
-// the finalize pass and the start of every phase touch consecutive slots, so
-// a field access of the wave is one contiguous 256-byte block.  32-bit word
-// offsets (fields * slots < 2^32, checked on the host) keep each access one
-// VGPR offset from a scalar base.
-template <int D>
-struct PoolView {
-    uint32_t* base;
-    uint32_t total;
-    __device__ __forceinline__ float& f(int fld, uint32_t g) const { return ((float*)base)[(uint32_t)fld * total + g]; }
-    __device__ __forceinline__ int32_t& i(int fld, uint32_t g) const { return ((int32_t*)base)[(uint32_t)fld * total + g]; }
-    __device__ __forceinline__ uint32_t& u(int fld, uint32_t g) const { return base[(uint32_t)fld * total + g]; }
-    __device__ __forceinline__ uint64_t wid(uint32_t g) const
-    {
-        return (uint64_t)u(PoolField<D>::WLO, g) | ((uint64_t)u(PoolField<D>::WHI, g) << 32);
-    }
-};
-
-__device__ __forceinline__ uint64_t wave_uniform_u64(uint64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ Stream walk_stream(const WalkParams& P, uint64_t wid)
-{
-    Stream rs;
-    rs.k0 = P.key0;
-    rs.k1 = P.key1;
-    const uint64_t p = wid / (uint64_t)P.wpp;
-    rs.p = (uint32_t)p;
-    rs.j = (uint32_t)(P.walk_offset + (wid - p * (uint64_t)P.wpp));
-    return rs;
-}
-
-// memory written by one lane of the wave becomes visible to the others
-__device__ __forceinline__ void wave_sync()
-{
-    __threadfence_block();
-    __syncthreads();
-}
 
 // Lanes that have finished their query wait until at least this many are
 // waiting (or no lane is still traversing) before they store results and
@@ -1050,37 +928,38 @@ extern "C" int wost_set_launch(int32_t waves_per_cu)
     return WOST_OK;
 }
 
-extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const float* pts, int64_t n_points,
-                          int32_t wpp, uint64_t seed, uint64_t walk_offset, const wost_guide* guide, double* sum,
-                          double* sum_sq, int64_t* count, float* walk_value, int32_t* walk_steps,
-                          const wost_records* rec, void* workspace, int64_t ws_bytes, uint64_t* dev_counters,
-                          void* stream)
+namespace wost {
+
+// Checks a solve's arguments and fills the launch parameters both solvers
+// share (geometry, fields, problem, random streams, guide, records, output
+// buffers); `who` names the entry point in error messages.
+int prepare_solve(const char* who, const wost_geom* geom, const wost_problem* pb, const float* pts, int64_t n_points,
+                  int32_t wpp, uint64_t seed, uint64_t walk_offset, const wost_guide* guide, double* sum,
+                  double* sum_sq, int64_t* count, float* walk_value, int32_t* walk_steps, const wost_records* rec,
+                  void* workspace, uint64_t* dev_counters, WalkParams& P)
 {
     if (!geom || !pb || !pts || !sum || !sum_sq || !count || !workspace || !dev_counters) {
-        set_error("wost_solve: NULL argument");
+        set_error("%s: NULL argument", who);
         return WOST_EINVAL;
     }
-    if (!geom->dev) { set_error("wost_solve: geometry not uploaded"); return WOST_ESTATE; }
-    if (geom->n_dir == 0) { set_error("wost_solve: the boundary has no Dirichlet part (walks never end)"); return WOST_EINVAL; }
-    if (n_points <= 0 || wpp <= 0) { set_error("wost_solve: n_points and wpp must be positive"); return WOST_EINVAL; }
+    if (!geom->dev) { set_error("%s: geometry not uploaded", who); return WOST_ESTATE; }
+    if (geom->n_dir == 0) { set_error("%s: the boundary has no Dirichlet part (walks never end)", who); return WOST_EINVAL; }
+    if (n_points <= 0 || wpp <= 0) { set_error("%s: n_points and wpp must be positive", who); return WOST_EINVAL; }
     if (n_points > 0xFFFFFFFFll || walk_offset + (uint64_t)wpp > 0xFFFFFFFFull) {
-        set_error("wost_solve: point index and walk index must fit 32 bits");
+        set_error("%s: point index and walk index must fit 32 bits", who);
         return WOST_EUNSUPPORTED;
     }
-    const int64_t need = wost_solve_workspace_bytes(geom, n_points, wpp);
-    if (ws_bytes < need) { set_error("wost_solve: workspace %lld < %lld bytes", (long long)ws_bytes, (long long)need); return WOST_ESIZE; }
     if (!(pb->eps > 0.f) || pb->max_steps < 0 || !(pb->rr_q > 0.f && pb->rr_q <= 1.f) || pb->r_min < 0.f) {
-        set_error("wost_solve: need eps > 0, max_steps >= 0, 0 < rr_q <= 1, r_min >= 0");
+        set_error("%s: need eps > 0, max_steps >= 0, 0 < rr_q <= 1, r_min >= 0", who);
         return WOST_EINVAL;
     }
     const bool guided = pb->sampling != WOST_SAMPLING_UNIFORM;
-    if (pb->sampling < 0 || pb->sampling > WOST_SAMPLING_GUIDED_ONLY) { set_error("wost_solve: unknown sampling mode"); return WOST_EINVAL; }
-    if (guided != (guide != nullptr)) { set_error("wost_solve: guide must be given iff sampling is not UNIFORM"); return WOST_EINVAL; }
+    if (pb->sampling < 0 || pb->sampling > WOST_SAMPLING_GUIDED_ONLY) { set_error("%s: unknown sampling mode", who); return WOST_EINVAL; }
+    if (guided != (guide != nullptr)) { set_error("%s: guide must be given iff sampling is not UNIFORM", who); return WOST_EINVAL; }
     if (pb->sampling == WOST_SAMPLING_MIS_FIXED && !(pb->c_fixed >= 0.f && pb->c_fixed <= 1.f)) {
-        set_error("wost_solve: c_fixed must be in [0, 1]");
+        set_error("%s: c_fixed must be in [0, 1]", who);
         return WOST_EINVAL;
     }
-    WalkParams P;
     memset(&P, 0, sizeof(P));
     P.geom = geom->devgeom();
     const int dim = geom->dim;
@@ -1111,8 +990,8 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     if (guided && guide && (pb->reflect != 0) != (guide->dev.reflect != 0)) {
         // the training loss reads the guide's setting, so a solve that draws
         // otherwise would train against another density than it sampled
-        set_error("wost_solve: problem.reflect = %d but the guide's reflection setting is %d "
-                  "(wost_guide_set_reflect)", pb->reflect != 0, guide->dev.reflect != 0);
+        set_error("%s: problem.reflect = %d but the guide's reflection setting is %d "
+                  "(wost_guide_set_reflect)", who, pb->reflect != 0, guide->dev.reflect != 0);
         return WOST_EINVAL;
     }
     if (guided) {
@@ -1123,12 +1002,41 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
         P.guide.reflect = pb->reflect != 0;
     }
     if (rec) {
-        if (!guided) { set_error("wost_solve: training records need a guided sampling mode"); return WOST_EINVAL; }
-        if (!rec->data || !rec->count || rec->capacity < 0) { set_error("wost_solve: bad record buffer"); return WOST_EINVAL; }
+        if (!guided) { set_error("%s: training records need a guided sampling mode", who); return WOST_EINVAL; }
+        if (!rec->data || !rec->count || rec->capacity < 0) { set_error("%s: bad record buffer", who); return WOST_EINVAL; }
         P.rec.data = rec->data;
         P.rec.capacity = rec->capacity;
         P.rec.count = (unsigned long long*)rec->count;
     }
+    return WOST_OK;
+}
+
+int walk_num_cu() { return num_cu(); }
+
+void launch_reduce_points(const WalkParams& P, double* sum, double* sum_sq, int64_t* count, hipStream_t s)
+{
+    const int rgrid = (int)((P.n_points + 3) / 4);
+    hipLaunchKernelGGL(reduce_points, dim3(rgrid), dim3(256), 0, s, P.slot_value, P.n_points, P.wpp, sum, sum_sq,
+                       count);
+}
+
+}  // namespace wost
+
+extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const float* pts, int64_t n_points,
+                          int32_t wpp, uint64_t seed, uint64_t walk_offset, const wost_guide* guide, double* sum,
+                          double* sum_sq, int64_t* count, float* walk_value, int32_t* walk_steps,
+                          const wost_records* rec, void* workspace, int64_t ws_bytes, uint64_t* dev_counters,
+                          void* stream)
+{
+    WalkParams P;
+    int rc = prepare_solve("wost_solve", geom, pb, pts, n_points, wpp, seed, walk_offset, guide, sum, sum_sq, count,
+                           walk_value, walk_steps, rec, workspace, dev_counters, P);
+    if (rc != WOST_OK) return rc;
+    const int64_t need = wost_solve_workspace_bytes(geom, n_points, wpp);
+    if (ws_bytes < need) { set_error("wost_solve: workspace %lld < %lld bytes", (long long)ws_bytes, (long long)need); return WOST_ESIZE; }
+    const bool guided = pb->sampling != WOST_SAMPLING_UNIFORM;
+    const int dim = geom->dim;
+    uint8_t* ws = (uint8_t*)workspace;
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, P.work, 1);
     using WalkFn = void (*)(const WalkParams);
@@ -1176,8 +1084,7 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     // about eight reservations per wave over the whole call, at least one lane's worth each
     P.chunk = std::max<uint64_t>(64, std::min<uint64_t>(4096, P.n_walks / ((uint64_t)grid * 8)));
     hipLaunchKernelGGL(fn, dim3(grid), dim3(64), lds, s, P);
-    const int rgrid = (int)((n_points + 3) / 4);
-    hipLaunchKernelGGL(reduce_points, dim3(rgrid), dim3(256), 0, s, P.slot_value, n_points, wpp, sum, sum_sq, count);
+    launch_reduce_points(P, sum, sum_sq, count, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("wost_solve: launch failed: %s", hipGetErrorString(e)); return WOST_EHIP; }
     return WOST_OK;

@@ -63,8 +63,9 @@ class Timer:
 
 
 def online_solve(geom, problem, pts, wpp_total, guide: Guide, schedule: OnlineSchedule = None, seed=18944,
-                 acc=None, timer: Timer = None):
+                 acc=None, timer: Timer = None, engine="persistent"):
     """Run ``wpp_total`` walks per point with online guide training.
+    ``engine`` selects the walk solver (see ``api.solve``).
     Returns (accumulator, info)."""
     sch = schedule or OnlineSchedule()
     n = pts.shape[0]
@@ -86,7 +87,7 @@ def online_solve(geom, problem, pts, wpp_total, guide: Guide, schedule: OnlineSc
         rec.reset()
         timer.mark("walk0")
         api.solve(geom, problem, pts, w, seed=seed, walk_offset=done, guide=guide, acc=acc,
-                  walk_value=walk_value[: n * w], records=rec)
+                  walk_value=walk_value[: n * w], records=rec, engine=engine)
         timer.mark("walk1")
         tail_pass(rec, walk_value[: n * w])
         timer.mark("tail1")
@@ -111,7 +112,8 @@ def online_solve(geom, problem, pts, wpp_total, guide: Guide, schedule: OnlineSc
         done += w
     if done < wpp_total:
         timer.mark("walk0")
-        api.solve(geom, problem, pts, wpp_total - done, seed=seed, walk_offset=done, guide=guide, acc=acc)
+        api.solve(geom, problem, pts, wpp_total - done, seed=seed, walk_offset=done, guide=guide, acc=acc,
+                  engine=engine)
         timer.mark("walk1")
     torch.cuda.synchronize()
     info["wall_s"] = time.perf_counter() - t0
