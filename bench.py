@@ -212,11 +212,15 @@ def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2
 def run_engine_ab(W, online_solve, OnlineSchedule, s, geom, pts, u, args, reps=2):
     """The persistent fused walk kernel against the multi-kernel wavefront
     solver (one kernel per stage over compacted walk queues, the paper's own
-    GPU organisation) on the bench workload: uniform and guided online
-    solves, same seeds; prints one JSON line per engine."""
+    GPU organisation; guided network inline or on a second stream) on the
+    bench workload: uniform and guided online solves, same seeds; prints one
+    JSON line per engine."""
     import torch
 
-    for engine in ("persistent", "wavefront"):
+    from paper_2410_18944_amd import api
+
+    for engine, streams in (("persistent", 1), ("wavefront", 1), ("wavefront", 2)):
+        api.set_wavefront_streams(streams)
         rows = []
         for r in range(reps):
             seed = 700 + r
@@ -239,8 +243,10 @@ def run_engine_ab(W, online_solve, OnlineSchedule, s, geom, pts, u, args, reps=2
                              guided_steps_per_s=sg["steps"] / t_g,
                              guided_rel_mse=rel_mse(acc_g.estimates()[0].cpu().numpy(), u)))
         out = {k: float(np.mean([r[k] for r in rows])) for k in rows[0]}
-        out.update(engine=engine, reps=reps, wpp=args.wpp, points=int(pts.shape[0]))
+        out.update(engine=engine, guided_streams=streams if engine == "wavefront" else None, reps=reps,
+                   wpp=args.wpp, points=int(pts.shape[0]))
         print(json.dumps(out), flush=True)
+    api.set_wavefront_streams(1)
 
 
 def main():

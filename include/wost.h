@@ -221,13 +221,23 @@ int wost_solve(const wost_geom* geom, const wost_problem* problem, const float* 
  * per stage (closest Dirichlet point, silhouette and radius, guided direction
  * batched over all stepping walks, Neumann sample and its visibility, source
  * point and its visibility, first hit, update), over queues of walk ids that
- * each stage compacts for the next.  Arguments, outputs and errors as
+ * each stage compacts for the next.  With two streams set
+ * (wost_set_wavefront_streams), guided solves split the walks into two
+ * halves and run the network of one half on a second stream (created by the
+ * library once per device, default priority) while the caller's stream runs
+ * the geometric stages of the other half.  Arguments, outputs and errors as
  * wost_solve; walks use the same random words and traversal code, so per-walk
  * values and step counts agree with wost_solve's.  Unlike wost_solve it
  * waits on `stream`: the host reads the live-walk count back every eight
  * steps and stops when it reaches zero.  Traversal-cost counters
  * (wost_set_cost_counters) are not supported (WOST_EUNSUPPORTED).  Kept as
  * the baseline the persistent kernel is measured against. */
+/* Streams of guided wavefront solves: 1 (default; every stage on the
+ * caller's stream) or 2 (the network on a second stream, overlapping the
+ * geometric stages of the other half of the walks, as in Sec. 5.2 "System
+ * Integration").  Process wide; results do not depend on it.  Other values:
+ * WOST_EINVAL. */
+int wost_set_wavefront_streams(int32_t n_streams);
 int64_t wost_solve_wavefront_workspace_bytes(const wost_geom* geom, int64_t n_points, int32_t wpp);
 int wost_solve_wavefront(const wost_geom* geom, const wost_problem* problem, const float* pts, int64_t n_points,
                          int32_t wpp, uint64_t seed, uint64_t walk_offset, const wost_guide* guide, double* sum,

@@ -72,6 +72,7 @@ SIGNATURES = {
     "wost_solve_wavefront": (_I, [_P, C.POINTER(wost_problem), _P, _I64, _I32, _U64, _U64, _P, _P, _P, _P, _P,
                                   _P, C.POINTER(wost_records), _P, _I64, _P, _P]),
     "wost_solve_wavefront_workspace_bytes": (_I64, [_P, _I64, _I32]),
+    "wost_set_wavefront_streams": (_I, [_I32]),
     "wost_set_launch": (_I, [_I32]),
     "wost_set_walk_pool": (_I, [_I32, _I32]),
     "wost_set_cost_counters": (_I, [_P]),

@@ -219,6 +219,12 @@ def solve(geom, problem, pts, wpp, seed=18944, walk_offset=0, guide=None, acc=No
     return acc
 
 
+def set_wavefront_streams(n_streams):
+    """Streams of guided wavefront solves: 1 (default) or 2 (the network on
+    its own stream, overlapping the other half's geometric stages)."""
+    L.check(L.load().wost_set_wavefront_streams(int(n_streams)), "wost_set_wavefront_streams")
+
+
 def set_walk_pool(slots_per_wave=0, refill_batch=0):
     """Walk slots per persistent wave (multiple of 64; 0 = default 384) and
     the number of finished lanes that refill together (0 = default 32)."""

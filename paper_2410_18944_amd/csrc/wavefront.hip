@@ -5,8 +5,10 @@
 // stage (closest Dirichlet point, silhouette and radius, guided direction,
 // Neumann sample and visibility, source point and visibility, first hit,
 // update), each over a compacted queue of walk ids that the previous stage
-// appended to.  The guide is evaluated for the whole step queue in one
-// batched kernel.  The host enqueues steps until the live queue is empty.
+// appended to.  The guide is evaluated for a whole step queue in one batched
+// kernel, optionally on a second stream where it overlaps the geometric
+// stages of the other half of the walks.  The host enqueues steps until the
+// live queues are empty.
 //
 // Walks draw the same random words (per walk and step) and run the same
 // traversal code as the persistent kernel, so per-walk results agree with it.
@@ -72,13 +74,15 @@ __global__ void wf_begin_step(uint32_t* cnt, int cur)
     }
 }
 
+// walks [first, first + count) start; their ids fill the first live queue
 template <int D>
-__global__ __launch_bounds__(64) void wf_init(const WalkParams P, const WfQueues Q)
+__global__ __launch_bounds__(64) void wf_init(const WalkParams P, const WfQueues Q, uint32_t first, uint32_t count)
 {
     using F = PoolField<D>;
     const PoolView<D> pv{P.pool, (uint32_t)P.pool_total};
-    for (uint64_t id = (uint64_t)blockIdx.x * 64 + threadIdx.x; id < P.n_walks; id += (uint64_t)gridDim.x * 64) {
-        const uint32_t g = (uint32_t)id;
+    for (uint32_t j = blockIdx.x * 64 + threadIdx.x; j < count; j += gridDim.x * 64) {
+        const uint32_t g = first + j;
+        const uint64_t id = g;
         const uint64_t p = id / (uint64_t)P.wpp;
 #pragma unroll
         for (int i = 0; i < D; ++i) { pv.f(F::X + i, g) = P.pts[p * D + i]; pv.f(F::NIN + i, g) = 0.f; }
@@ -88,7 +92,7 @@ __global__ __launch_bounds__(64) void wf_init(const WalkParams P, const WfQueues
         pv.i(F::K, g) = 0;
         pv.u(F::WLO, g) = (uint32_t)id;
         pv.u(F::WHI, g) = (uint32_t)(id >> 32);
-        Q.act[0][g] = g;
+        Q.act[0][j] = g;
     }
 }
 
@@ -554,14 +558,26 @@ __global__ __launch_bounds__(64) void wf_update(const WalkParams P, const WfQueu
     wf_tally(P.counters, 6, n_drop);
 }
 
+// one step of a queue set, in three parts: up to the radius, the guided
+// direction, and the rest (the guide part may run on another stream)
 template <int D, bool GUIDED>
-static void enqueue_step(const WalkParams& P, const WfQueues& Q, int cur, int grid, size_t lds_stack, size_t lds_guide,
-                         bool has_h, bool has_f, hipStream_t s)
+static void enqueue_front(const WalkParams& P, const WfQueues& Q, int cur, int grid, size_t lds_stack, hipStream_t s)
 {
     hipLaunchKernelGGL(wf_begin_step, dim3(1), dim3(64), 0, s, Q.cnt, cur);
     hipLaunchKernelGGL(wf_dirichlet<D>, dim3(grid), dim3(64), lds_stack, s, P, Q, cur);
     hipLaunchKernelGGL((wf_silhouette<D, GUIDED>), dim3(grid), dim3(64), lds_stack, s, P, Q);
-    if (GUIDED) hipLaunchKernelGGL(wf_guide<D>, dim3(grid), dim3(64), lds_guide, s, P, Q);
+}
+
+template <int D>
+static void enqueue_guide(const WalkParams& P, const WfQueues& Q, int grid, size_t lds_guide, hipStream_t s)
+{
+    hipLaunchKernelGGL(wf_guide<D>, dim3(grid), dim3(64), lds_guide, s, P, Q);
+}
+
+template <int D, bool GUIDED>
+static void enqueue_back(const WalkParams& P, const WfQueues& Q, int cur, int grid, size_t lds_stack, bool has_h,
+                         bool has_f, hipStream_t s)
+{
     if (has_h) {
         hipLaunchKernelGGL(wf_neumann<D>, dim3(grid), dim3(64), 0, s, P, Q);
         hipLaunchKernelGGL(wf_neumann_visibility<D>, dim3(grid), dim3(64), lds_stack, s, P, Q);
@@ -574,6 +590,57 @@ static void enqueue_step(const WalkParams& P, const WfQueues& Q, int cur, int gr
     hipLaunchKernelGGL((wf_update<D, GUIDED>), dim3(grid), dim3(64), 0, s, P, Q, cur);
 }
 
+struct WfLaunch {
+    int grid;
+    size_t lds_stack, lds_guide;
+    bool has_h, has_f;
+    hipStream_t s, s2;          // the caller's stream; the inference stream (guided)
+    hipEvent_t front[2], inf[2];
+};
+
+// One step of every live walk.  With one stream, one queue set runs all its
+// stages on the caller's stream.  With the inference stream (guided, two
+// streams), the walks are split into two halves with their own queues; the
+// network for one half runs on the inference stream while the caller's
+// stream runs the other half's geometric stages.
+template <int D, bool GUIDED>
+static void enqueue_step(const WalkParams& P, const WfQueues* Q, int nq, int cur, const WfLaunch& L)
+{
+    if (!GUIDED || !L.s2) {
+        enqueue_front<D, GUIDED>(P, Q[0], cur, L.grid, L.lds_stack, L.s);
+        if (GUIDED) enqueue_guide<D>(P, Q[0], L.grid, L.lds_guide, L.s);
+        enqueue_back<D, GUIDED>(P, Q[0], cur, L.grid, L.lds_stack, L.has_h, L.has_f, L.s);
+        return;
+    }
+    for (int h = 0; h < nq; ++h) {
+        enqueue_front<D, true>(P, Q[h], cur, L.grid, L.lds_stack, L.s);
+        hipEventRecord(L.front[h], L.s);
+        hipStreamWaitEvent(L.s2, L.front[h], 0);
+        enqueue_guide<D>(P, Q[h], L.grid, L.lds_guide, L.s2);
+        hipEventRecord(L.inf[h], L.s2);
+    }
+    for (int h = 0; h < nq; ++h) {
+        hipStreamWaitEvent(L.s, L.inf[h], 0);
+        enqueue_back<D, true>(P, Q[h], cur, L.grid, L.lds_stack, L.has_h, L.has_f, L.s);
+    }
+}
+
+// streams of a guided wavefront solve: 1 (every stage on the caller's
+// stream) or 2 (the network on its own stream, overlapping the other half's
+// geometric stages)
+static int g_wf_streams = 1;
+
+// the inference stream, created once per device at default priority
+static hipStream_t inference_stream()
+{
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+        streams[dev] = nullptr;
+    return streams[dev];
+}
+
 static inline int64_t wf_align256(int64_t v) { return (v + 255) & ~int64_t(255); }
 static inline int wf_words(int dim) { return dim == 2 ? PoolField<2>::WORDS : PoolField<3>::WORDS; }
 
@@ -581,12 +648,24 @@ static inline int wf_words(int dim) { return dim == 2 ? PoolField<2>::WORDS : Po
 
 using namespace wost;
 
+extern "C" int wost_set_wavefront_streams(int32_t n_streams)
+{
+    if (n_streams != 1 && n_streams != 2) {
+        set_error("wost_set_wavefront_streams: 1 or 2 streams");
+        return WOST_EINVAL;
+    }
+    g_wf_streams = n_streams;
+    return WOST_OK;
+}
+
 extern "C" int64_t wost_solve_wavefront_workspace_bytes(const wost_geom* geom, int64_t n_points, int32_t wpp)
 {
     if (!geom || n_points < 0 || wpp <= 0) return -1;
     const int64_t n = n_points * (int64_t)wpp;
-    // counters | per-walk values | walk state | 5 queues
-    return 256 + wf_align256(n * 4) + wf_align256(n * wf_words(geom->dim) * 4) + 5 * wf_align256(n * 4);
+    // counters | per-walk values | walk state | 5 queues per half (two halves
+    // for guided solves, each sized for its own walks)
+    return 256 + wf_align256(n * 4) + wf_align256(n * wf_words(geom->dim) * 4) + 5 * (wf_align256((n + 1) / 2 * 4) +
+                                                                                      wf_align256(n / 2 * 4));
 }
 
 extern "C" int wost_solve_wavefront(const wost_geom* geom, const wost_problem* pb, const float* pts, int64_t n_points,
@@ -615,54 +694,93 @@ extern "C" int wost_solve_wavefront(const wost_geom* geom, const wost_problem* p
         return WOST_EUNSUPPORTED;
     }
     const bool guided = pb->sampling != WOST_SAMPLING_UNIFORM;
-    const bool has_h = P.h.kind != WOST_FIELD_ZERO, has_f = P.f.kind != WOST_FIELD_ZERO;
     uint8_t* ws = (uint8_t*)workspace;
-    const int64_t vbytes = wf_align256(n * 4), qbytes = wf_align256(n * 4);
+    const int64_t vbytes = wf_align256(n * 4);
     P.pool = (uint32_t*)(ws + 256 + vbytes);
     P.pool_total = n;
     P.pool_n = 0;
     uint8_t* qb = ws + 256 + vbytes + wf_align256(n * wf_words(dim) * 4);
-    WfQueues Q;
-    Q.act[0] = (uint32_t*)qb;
-    Q.act[1] = (uint32_t*)(qb + qbytes);
-    Q.step = (uint32_t*)(qb + 2 * qbytes);
-    Q.vis = (uint32_t*)(qb + 3 * qbytes);
-    Q.svis = (uint32_t*)(qb + 4 * qbytes);
-    Q.cnt = (uint32_t*)ws;     // the first 256 bytes: queue lengths
+    // guided solves on two streams run two halves of the walks
+    const bool two = guided && n > 1 && g_wf_streams == 2;
+    const int nq = two ? 2 : 1;
+    const int64_t cnt_h[2] = {nq == 2 ? (n + 1) / 2 : n, nq == 2 ? n / 2 : 0};
+    WfQueues Q[2];
+    for (int h = 0; h < nq; ++h) {
+        const int64_t qbytes = wf_align256(cnt_h[h] * 4);
+        Q[h].act[0] = (uint32_t*)qb;
+        Q[h].act[1] = (uint32_t*)(qb + qbytes);
+        Q[h].step = (uint32_t*)(qb + 2 * qbytes);
+        Q[h].vis = (uint32_t*)(qb + 3 * qbytes);
+        Q[h].svis = (uint32_t*)(qb + 4 * qbytes);
+        Q[h].cnt = (uint32_t*)(ws + 64 * h);     // queue lengths in the first 256 bytes
+        qb += 5 * qbytes;
+    }
     hipStream_t s = (hipStream_t)stream;
-    const size_t lds_stack = sizeof(uint2) * (size_t)geom->stack_entries * kWave;
-    const size_t lds_guide = guided ? sizeof(float) * kWave * (size_t)guide_out_stride(P.guide) : 0;
+    WfLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.s = s;
+    L.has_h = P.h.kind != WOST_FIELD_ZERO;
+    L.has_f = P.f.kind != WOST_FIELD_ZERO;
+    L.lds_stack = sizeof(uint2) * (size_t)geom->stack_entries * kWave;
+    L.lds_guide = guided ? sizeof(float) * kWave * (size_t)guide_out_stride(P.guide) : 0;
     // enough waves to keep every CU busy on a long queue; stages read their
     // queue length on the device, so the grid does not follow it
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 63) / 64, (int64_t)walk_num_cu() * 16));
+    L.grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 63) / 64, (int64_t)walk_num_cu() * 16));
+    bool events = false;
+    if (two) {
+        L.s2 = inference_stream();
+        events = L.s2 != nullptr;
+        for (int h = 0; h < 2 && events; ++h)
+            events = hipEventCreateWithFlags(&L.front[h], hipEventDisableTiming) == hipSuccess &&
+                     hipEventCreateWithFlags(&L.inf[h], hipEventDisableTiming) == hipSuccess;
+        if (!events) {
+            set_error("wost_solve_wavefront: could not create the inference stream or its events");
+            return WOST_EHIP;
+        }
+    }
     const int igrid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 63) / 64, (int64_t)walk_num_cu() * 32));
-    hipLaunchKernelGGL(wf_set_counts, dim3(1), dim3(64), 0, s, Q.cnt, (uint32_t)n);
-    if (dim == 2) hipLaunchKernelGGL(wf_init<2>, dim3(igrid), dim3(64), 0, s, P, Q);
-    else hipLaunchKernelGGL(wf_init<3>, dim3(igrid), dim3(64), 0, s, P, Q);
+    int64_t first = 0;
+    for (int h = 0; h < nq; ++h) {
+        hipLaunchKernelGGL(wf_set_counts, dim3(1), dim3(64), 0, s, Q[h].cnt, (uint32_t)cnt_h[h]);
+        if (dim == 2) hipLaunchKernelGGL(wf_init<2>, dim3(igrid), dim3(64), 0, s, P, Q[h], (uint32_t)first, (uint32_t)cnt_h[h]);
+        else hipLaunchKernelGGL(wf_init<3>, dim3(igrid), dim3(64), 0, s, P, Q[h], (uint32_t)first, (uint32_t)cnt_h[h]);
+        first += cnt_h[h];
+    }
     // every step ends a walk whose step count has reached max_steps, so
-    // max_steps + 1 steps finish every walk; the live count is read back
+    // max_steps + 1 steps finish every walk; the live counts are read back
     // every few steps to stop early
     const int64_t max_iter = (int64_t)P.max_steps + 1;
     int cur = 0;
+    int rc_loop = WOST_OK;
     for (int64_t it = 0; it < max_iter; ++it) {
         if (dim == 2) {
-            if (guided) enqueue_step<2, true>(P, Q, cur, grid, lds_stack, lds_guide, has_h, has_f, s);
-            else enqueue_step<2, false>(P, Q, cur, grid, lds_stack, lds_guide, has_h, has_f, s);
+            if (guided) enqueue_step<2, true>(P, Q, nq, cur, L);
+            else enqueue_step<2, false>(P, Q, nq, cur, L);
         } else {
-            if (guided) enqueue_step<3, true>(P, Q, cur, grid, lds_stack, lds_guide, has_h, has_f, s);
-            else enqueue_step<3, false>(P, Q, cur, grid, lds_stack, lds_guide, has_h, has_f, s);
+            if (guided) enqueue_step<3, true>(P, Q, nq, cur, L);
+            else enqueue_step<3, false>(P, Q, nq, cur, L);
         }
         cur ^= 1;
         if ((it & 7) == 7 || it + 1 == max_iter) {
-            uint32_t live = 0;
-            if (hipMemcpyAsync(&live, Q.cnt + cur, sizeof(live), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess) {
+            uint32_t live[2] = {0, 0};
+            bool ok = true;
+            for (int h = 0; h < nq && ok; ++h)
+                ok = hipMemcpyAsync(&live[h], Q[h].cnt + cur, sizeof(uint32_t), hipMemcpyDeviceToHost, s) == hipSuccess;
+            if (!ok || hipStreamSynchronize(s) != hipSuccess) {
                 set_error("wost_solve_wavefront: %s", hipGetErrorString(hipGetLastError()));
-                return WOST_EHIP;
+                rc_loop = WOST_EHIP;
+                break;
             }
-            if (live == 0) break;
+            if (live[0] + live[1] == 0) break;
         }
     }
+    if (events) {
+        for (int h = 0; h < 2; ++h) {
+            hipEventDestroy(L.front[h]);
+            hipEventDestroy(L.inf[h]);
+        }
+    }
+    if (rc_loop != WOST_OK) return rc_loop;
     launch_reduce_points(P, sum, sum_sq, count, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("wost_solve_wavefront: launch failed: %s", hipGetErrorString(e)); return WOST_EHIP; }

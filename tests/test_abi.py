@@ -167,6 +167,14 @@ def test_upload_and_solve_reject_bad_arguments_without_launch(lib):
     assert rc == -4
     assert L.wost_geom_upload(h, None, 0, None) == -1
     assert L.wost_solve_workspace_bytes(h, 100, 8) >= 100 * 8 * 4
+    # the wavefront solver takes the same checks, and a workspace that holds
+    # every walk's state and its queues
+    rc = L.wost_solve_wavefront(h, C.byref(pb), dummy, 10, 4, 1, 0, None, dummy, dummy, dummy, None, None, None,
+                                dummy, 1 << 20, dummy, None)
+    assert rc == -4
+    assert L.wost_solve_wavefront_workspace_bytes(h, 100, 8) >= 100 * 8 * (4 + 20 + 4 * 26)  # 26 state words in 2D
+    assert L.wost_set_wavefront_streams(3) < 0 and L.wost_set_wavefront_streams(0) < 0
+    assert L.wost_set_wavefront_streams(2) == 0 and L.wost_set_wavefront_streams(1) == 0
     L.wost_geom_free(h)
 
 

@@ -81,15 +81,17 @@ def test_wavefront_matches_persistent_walk_by_walk(W, name):
     assert a["stats"]["steps"] == int(a["walk_steps"].sum())
 
 
-@pytest.mark.parametrize("reflect", [True, False])
-def test_wavefront_guided_matches_persistent_with_records(W, reflect):
+@pytest.mark.parametrize("reflect,streams", [(True, 1), (False, 1), (True, 2)])
+def test_wavefront_guided_matches_persistent_with_records(W, reflect, streams):
     from tests.test_gpu_guide import _guide_setup
+    from paper_2410_18944_amd import api
+    api.set_wavefront_streams(streams)
     s = rounded(scenes.scene_c2())
     pts = s.points[::41]
     wpp = 8
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=81)
     g.reflect = reflect
-    say("wavefront vs persistent, guided", len(pts), "x", wpp, "reflect", reflect)
+    say("wavefront vs persistent, guided", len(pts), "x", wpp, "reflect", reflect, "streams", streams)
     recs = {}
     out = {}
     for eng in ("wavefront", "persistent"):
@@ -108,14 +110,20 @@ def test_wavefront_guided_matches_persistent_with_records(W, reflect):
     np.testing.assert_array_equal(a["slot"], b["slot"])
     for k in ("x", "nu", "n", "p_sample", "prefix", "t_next"):
         np.testing.assert_allclose(a[k], b[k], rtol=1e-5, atol=1e-6, err_msg=k)
+    api.set_wavefront_streams(1)
 
 
 def test_wavefront_3d_guided_matches_persistent(W):
     from tests.test_gpu_guide import _guide_setup, _scene_3d
+    from paper_2410_18944_amd import api
     s = _scene_3d()
     g, cfg, rcfg, p16 = _guide_setup(W, s, seed=82, log2_table=14)
-    say("wavefront vs persistent, guided 3D")
-    a = _run(W, s, s.points, 16, "wavefront", guide=g, sampling="mis_learned")
+    say("wavefront vs persistent, guided 3D, two streams")
+    api.set_wavefront_streams(2)
+    try:
+        a = _run(W, s, s.points, 16, "wavefront", guide=g, sampling="mis_learned")
+    finally:
+        api.set_wavefront_streams(1)
     b = _run(W, s, s.points, 16, "persistent", guide=g, sampling="mis_learned")
     _same_walks(a, b, "guided 3D")
 
@@ -152,6 +160,7 @@ def test_wavefront_edge_cases(W):
     d = _run(W, s, s.points[:64], 4, "persistent", max_steps=0)
     assert np.all(c["walk_steps"] == 1)
     _same_walks(c, d, "max_steps 0")
+    from paper_2410_18944_amd import api
     # traversal-cost counters are kept by the persistent kernel only
     from paper_2410_18944_amd import api
     cost = torch.zeros(18, dtype=torch.int64, device="cuda")
