@@ -357,6 +357,39 @@ int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin,
                           const wost_adam* opt, float* loss_out, void* workspace, int64_t ws_bytes,
                           void* stream);
 
+/* ------------------------------------------------------------ GPU hierarchy build
+ * Linear BVH built on the GPU (Karras 2012; the paper's query library uses a
+ * linear BVH, Sec. 5.3) over a primitive set for closest-point queries, in
+ * the same four-wide node layout as the Dirichlet hierarchy that
+ * wost_build_bvh writes.  Primitives are device float4 records: a 2D
+ * segment (ax, ay, bx, by) per float4, a 3D triangle (a, b, c) packed in
+ * three float4 (ax ay az bx | by bz cx cy | cz - - -).
+ *
+ * wost_lbvh_sizes: bytes of the node buffer (at most n - 1 four-wide nodes),
+ * of the sorted primitive buffer and of the build workspace, for n >= 1
+ * primitives (n below 2^25 - 64); WOST_EINVAL otherwise. */
+int wost_lbvh_sizes(int32_t dim, int64_t n, int64_t* node_bytes, int64_t* prim_bytes, int64_t* ws_bytes);
+/* Builds the hierarchy: Morton codes of the primitive centroids, radix sort,
+ * binary radix tree, node boxes bottom-up, then four-wide nodes level by
+ * level; a subtree of at most leaf_size (1..64) primitives becomes a leaf.
+ * Outputs (caller-owned device buffers): nodes [node_bytes], prims_sorted
+ * [prim_bytes] (the primitives in leaf order), orig int32 [n] (caller index
+ * of each sorted primitive); host outputs *n_nodes and *levels (four-wide
+ * depth).  workspace: device, 256-byte aligned, >= ws_bytes; prims, nodes and
+ * prims_sorted 16-byte aligned.  Waits on `stream` (the level-by-level
+ * collapse reads each level's size back). */
+int wost_lbvh_build(int32_t dim, const float* prims, int64_t n, int32_t leaf_size, float* nodes,
+                    float* prims_sorted, int32_t* orig, int32_t* n_nodes, int32_t* levels, void* workspace,
+                    int64_t ws_bytes, void* stream);
+/* Closest primitive to each of m points (device [m][dim]) in a hierarchy
+ * from wost_lbvh_build: dist device float [m] (Euclidean distance), prim
+ * device int32 [m] (caller index, -1 if none).  The traversal is the walk's
+ * closest-Dirichlet-point query; its stack takes 3 (levels - 1) + 1 LDS
+ * entries per lane (WOST_EUNSUPPORTED beyond 64 KB per workgroup). */
+int wost_lbvh_closest(int32_t dim, const float* nodes, int32_t n_nodes, const float* prims_sorted,
+                      const int32_t* orig, int32_t n_prims, int32_t levels, const float* pts, int64_t m,
+                      float* dist, int32_t* prim, void* stream);
+
 /* ------------------------------------------------------------ launch tuning
  * Persistent walk workgroups (one wave each) per compute unit, 1..64, or 0
  * (the default) for as many as the launched kernel variant can keep resident

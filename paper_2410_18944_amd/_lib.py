@@ -73,6 +73,9 @@ SIGNATURES = {
                                   _P, C.POINTER(wost_records), _P, _I64, _P, _P]),
     "wost_solve_wavefront_workspace_bytes": (_I64, [_P, _I64, _I32]),
     "wost_set_wavefront_streams": (_I, [_I32]),
+    "wost_lbvh_sizes": (_I, [_I32, _I64, _P, _P, _P]),
+    "wost_lbvh_build": (_I, [_I32, _P, _I64, _I32, _P, _P, _P, _P, _P, _P, _I64, _P]),
+    "wost_lbvh_closest": (_I, [_I32, _P, _I32, _P, _P, _I32, _I32, _P, _I64, _P, _P, _P]),
     "wost_set_launch": (_I, [_I32]),
     "wost_set_walk_pool": (_I, [_I32, _I32]),
     "wost_set_cost_counters": (_I, [_P]),

@@ -219,6 +219,42 @@ def solve(geom, problem, pts, wpp, seed=18944, walk_offset=0, guide=None, acc=No
     return acc
 
 
+class Lbvh:
+    """A closest-point hierarchy built on the GPU (wost_lbvh_build) over
+    primitives given as a device float32 tensor of float4 records (2D: one
+    (ax, ay, bx, by) per segment; 3D: three per triangle)."""
+
+    def __init__(self, dim, prims, leaf_size=4):
+        lib = L.load()
+        prims = prims.contiguous()
+        per = 4 if dim == 2 else 12
+        n = prims.numel() // per
+        nb, pb, wb = C.c_int64(), C.c_int64(), C.c_int64()
+        L.check(lib.wost_lbvh_sizes(int(dim), n, C.byref(nb), C.byref(pb), C.byref(wb)), "wost_lbvh_sizes")
+        dev = prims.device
+        self.dim, self.n = dim, n
+        self.nodes = torch.empty(nb.value // 4, dtype=torch.float32, device=dev)
+        self.prims = torch.empty(pb.value // 4, dtype=torch.float32, device=dev)
+        self.orig = torch.empty(n, dtype=torch.int32, device=dev)
+        ws = torch.empty(wb.value + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        nn, lv = C.c_int32(), C.c_int32()
+        L.check(lib.wost_lbvh_build(int(dim), _ptr(prims), n, int(leaf_size), _ptr(self.nodes), _ptr(self.prims),
+                                    _ptr(self.orig), C.byref(nn), C.byref(lv), C.c_void_p(ws.data_ptr() + off),
+                                    wb.value, _stream()), "wost_lbvh_build")
+        self.n_nodes, self.levels = nn.value, lv.value
+
+    def closest(self, pts):
+        pts = pts.contiguous()
+        m = pts.shape[0]
+        dist = torch.empty(m, dtype=torch.float32, device=pts.device)
+        prim = torch.empty(m, dtype=torch.int32, device=pts.device)
+        L.check(L.load().wost_lbvh_closest(self.dim, _ptr(self.nodes), self.n_nodes, _ptr(self.prims),
+                                           _ptr(self.orig), self.n, self.levels, _ptr(pts), m, _ptr(dist),
+                                           _ptr(prim), _stream()), "wost_lbvh_closest")
+        return dist, prim
+
+
 def set_wavefront_streams(n_streams):
     """Streams of guided wavefront solves: 1 (default) or 2 (the network on
     its own stream, overlapping the other half's geometric stages)."""
