@@ -249,6 +249,54 @@ def run_engine_ab(W, online_solve, OnlineSchedule, s, geom, pts, u, args, reps=2
     api.set_wavefront_streams(1)
 
 
+def run_lbvh(W, reps=5):
+    """GPU linear-BVH build against the host build of the same closest-point
+    hierarchy (the Dirichlet primitives of the two 3D workloads), and the
+    closest-point query rate of both on 2^20 points; one JSON line each."""
+    import torch
+
+    import scenes
+    from paper_2410_18944_amd.api import Lbvh
+
+    for name, make in (("C4", scenes.scene_c4), ("C5", scenes.scene_c5)):
+        s = make()
+        dp = s.prims[s.bc == 0]
+        v = np.asarray(s.verts, np.float32)
+        recs = np.concatenate([v[dp[:, 0]], v[dp[:, 1]], v[dp[:, 2]], np.zeros((len(dp), 3), np.float32)], 1)
+        t_recs = torch.as_tensor(recs, device="cuda").reshape(-1)
+        Lbvh(3, t_recs)          # warm-up (kernel loading)
+        torch.cuda.synchronize()
+        tg = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            bv = Lbvh(3, t_recs)
+            torch.cuda.synchronize()
+            tg.append(time.perf_counter() - t0)
+        th = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            geo = W.Geometry(3, s.verts, dp, np.zeros(len(dp), np.uint8))
+            torch.cuda.synchronize()
+            th.append(time.perf_counter() - t0)
+        rng = np.random.default_rng(5)
+        lo, hi = s.verts.min(0), s.verts.max(0)
+        q = torch.as_tensor(rng.uniform(lo, hi, (1 << 20, 3)).astype(np.float32), device="cuda")
+        rates = {}
+        for label, fn in (("lbvh", lambda: bv.closest(q)), ("host_bvh", lambda: geo.query(q, silhouette=False))):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(5):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            rates[label] = 5 * q.shape[0] / (e0.elapsed_time(e1) * 1e-3)
+        print(json.dumps({"workload": name, "primitives": int(len(dp)), "lbvh_build_ms": 1e3 * min(tg),
+                          "host_build_and_upload_ms": 1e3 * min(th), "lbvh_nodes": bv.n_nodes,
+                          "lbvh_levels": bv.levels, "closest_queries_per_s": rates}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +314,8 @@ def main():
     ap.add_argument("--engine-ab", action="store_true",
                     help="instead of the bench line: the persistent walk kernel against the multi-kernel "
                          "wavefront solver on the bench workload")
+    ap.add_argument("--lbvh", action="store_true",
+                    help="instead of the bench line: GPU linear-BVH build and query rate against the host build")
     ap.add_argument("--ablations", action="store_true",
                     help="instead of the bench line: sampling-mode ablations (K, selection c, reflection) and the "
                          "training-schedule sweep on the same workload, one JSON line per configuration")
@@ -300,6 +350,9 @@ def main():
     s = scenes.scene_c2(wpp=args.wpp)
     if args.guide_mlp:
         print(json.dumps({"guide_mlp": guide_mlp_rates(W, W.GuideConfig.for_scene(s))}))
+        return
+    if args.lbvh:
+        run_lbvh(W)
         return
     pts = torch.as_tensor(s.points, dtype=torch.float32, device="cuda")
     u = s.points[:, 0] ** 3 - 3 * s.points[:, 0] * s.points[:, 1] ** 2
