@@ -389,6 +389,16 @@ int wost_lbvh_build(int32_t dim, const float* prims, int64_t n, int32_t leaf_siz
 int wost_lbvh_closest(int32_t dim, const float* nodes, int32_t n_nodes, const float* prims_sorted,
                       const int32_t* orig, int32_t n_prims, int32_t levels, const float* pts, int64_t m,
                       float* dist, int32_t* prim, void* stream);
+/* Uses a hierarchy from wost_lbvh_build over the geometry's Dirichlet
+ * primitives (the same set, possibly moved) in place of the Dirichlet
+ * section of the uploaded image, for wost_solve, wost_solve_wavefront and
+ * wost_query; nodes NULL switches back to the image's own.  The buffers stay
+ * caller-owned and must outlive their use.  n_prims must equal the
+ * geometry's Dirichlet primitive count (else WOST_EINVAL), and the hierarchy
+ * at most 14 levels deep (the traversal stack of wost_query, else
+ * WOST_EUNSUPPORTED).  Host only. */
+int wost_geom_use_dirichlet_lbvh(wost_geom* g, const float* nodes, int32_t n_nodes, const float* prims_sorted,
+                                 const int32_t* orig, int32_t n_prims, int32_t levels);
 
 /* ------------------------------------------------------------ launch tuning
  * Persistent walk workgroups (one wave each) per compute unit, 1..64, or 0

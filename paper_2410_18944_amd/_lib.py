@@ -74,6 +74,7 @@ SIGNATURES = {
     "wost_solve_wavefront_workspace_bytes": (_I64, [_P, _I64, _I32]),
     "wost_set_wavefront_streams": (_I, [_I32]),
     "wost_lbvh_sizes": (_I, [_I32, _I64, _P, _P, _P]),
+    "wost_geom_use_dirichlet_lbvh": (_I, [_P, _P, _I32, _P, _P, _I32, _I32]),
     "wost_lbvh_build": (_I, [_I32, _P, _I64, _I32, _P, _P, _P, _P, _P, _P, _I64, _P]),
     "wost_lbvh_closest": (_I, [_I32, _P, _I32, _P, _P, _I32, _I32, _P, _I64, _P, _P, _P]),
     "wost_set_launch": (_I, [_I32]),

@@ -84,6 +84,18 @@ class Geometry:
             lib.wost_geom_free(self.h)
             self.h = None
 
+    def use_dirichlet_lbvh(self, bv=None):
+        """Walk and query over a GPU-built hierarchy ``bv`` (an ``Lbvh`` over
+        the same Dirichlet primitives) instead of the host-built one; None
+        switches back."""
+        lib = L.load()
+        if bv is None:
+            L.check(lib.wost_geom_use_dirichlet_lbvh(self.h, None, 0, None, None, 0, 0), "wost_geom_use_dirichlet_lbvh")
+        else:
+            L.check(lib.wost_geom_use_dirichlet_lbvh(self.h, _ptr(bv.nodes), bv.n_nodes, _ptr(bv.prims),
+                                                     _ptr(bv.orig), bv.n, bv.levels), "wost_geom_use_dirichlet_lbvh")
+        self._dir_lbvh = bv      # keeps the buffers alive while in use
+
     def query(self, pts, dirichlet=True, silhouette=True, ray_dir=None, ray_tmax=None, on_prim=None):
         lib = L.load()
         pts = pts.contiguous()

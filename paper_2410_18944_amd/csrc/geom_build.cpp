@@ -198,6 +198,15 @@ wost::DevGeom wost_geom::devgeom() const
         b[i]->n_nodes = sec[i].n_nodes;
         b[i]->n_prims = sec[i].n_prims;
     }
+    if (dir_dev.nodes) {
+        g.dir.nodes = (const float4*)dir_dev.nodes;
+        g.dir.prims = (const float4*)dir_dev.prims;
+        g.dir.pextra = nullptr;
+        g.dir.orig = dir_dev.orig;
+        g.dir.piece = nullptr;
+        g.dir.n_nodes = dir_dev.n_nodes;
+        g.dir.n_prims = dir_dev.n_prims;
+    }
     g.neu_id = off_neu_id >= 0 ? (const int32_t*)(base + off_neu_id) : nullptr;
     g.n_caller = n_caller;
     g.dim = dim;
@@ -208,6 +217,39 @@ wost::DevGeom wost_geom::devgeom() const
 }
 
 extern "C" const char* wost_last_error(void) { return wost::g_err.c_str(); }
+
+extern "C" int wost_geom_use_dirichlet_lbvh(wost_geom* g, const float* nodes, int32_t n_nodes,
+                                           const float* prims_sorted, const int32_t* orig, int32_t n_prims,
+                                           int32_t levels)
+{
+    if (!g) { set_error("wost_geom_use_dirichlet_lbvh: NULL geometry"); return WOST_EINVAL; }
+    if (!nodes) {
+        g->dir_dev = wost_geom::DirDev{};
+        return WOST_OK;
+    }
+    if (!prims_sorted || !orig || n_nodes < 1 || levels < 1) {
+        set_error("wost_geom_use_dirichlet_lbvh: need nodes, sorted primitives, orig, n_nodes >= 1, levels >= 1");
+        return WOST_EINVAL;
+    }
+    if (n_prims != g->n_dir) {
+        set_error("wost_geom_use_dirichlet_lbvh: %d primitives, the geometry has %lld Dirichlet primitives", n_prims,
+                  (long long)g->n_dir);
+        return WOST_EINVAL;
+    }
+    const int64_t stack = 3 * ((int64_t)levels - 1) + 1;
+    if (stack > kMaxStack) {
+        set_error("wost_geom_use_dirichlet_lbvh: %d levels need %lld stack entries (at most %d)", levels,
+                  (long long)stack, kMaxStack);
+        return WOST_EUNSUPPORTED;
+    }
+    g->dir_dev.nodes = nodes;
+    g->dir_dev.prims = prims_sorted;
+    g->dir_dev.orig = orig;
+    g->dir_dev.n_nodes = n_nodes;
+    g->dir_dev.n_prims = n_prims;
+    g->dir_dev.stack = (int32_t)stack;
+    return WOST_OK;
+}
 
 extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, const int32_t* prims,
                               int64_t n_prims, const uint8_t* bc, const wost_build_opts* opts,

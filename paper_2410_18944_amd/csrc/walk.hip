@@ -1048,7 +1048,7 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
         if (P.cost) fn = guided ? walk_kernel3g<true> : walk_kernel3u<true>;
         else fn = guided ? walk_kernel3g<false> : walk_kernel3u<false>;
     }
-    const size_t lds = walk_lds_bytes(guided, geom->stack_entries, guide_out_stride(P.guide));
+    const size_t lds = walk_lds_bytes(guided, geom->stack_need(), guide_out_stride(P.guide));
     int per_cu = g_waves_per_cu;
     if (per_cu == 0) {
         int nb = 0;

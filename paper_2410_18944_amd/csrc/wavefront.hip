@@ -721,7 +721,7 @@ extern "C" int wost_solve_wavefront(const wost_geom* geom, const wost_problem* p
     L.s = s;
     L.has_h = P.h.kind != WOST_FIELD_ZERO;
     L.has_f = P.f.kind != WOST_FIELD_ZERO;
-    L.lds_stack = sizeof(uint2) * (size_t)geom->stack_entries * kWave;
+    L.lds_stack = sizeof(uint2) * (size_t)geom->stack_need() * kWave;
     L.lds_guide = guided ? sizeof(float) * kWave * (size_t)guide_out_stride(P.guide) : 0;
     // enough waves to keep every CU busy on a long queue; stages read their
     // queue length on the device, so the grid does not follow it

@@ -101,7 +101,17 @@ struct wost_geom {
     int64_t n_caller = 0;
     void* dev = nullptr;    // caller buffer after upload
     int32_t* orig_host = nullptr;    // concatenated: dir, neu prims -> caller ids
+    // a Dirichlet hierarchy built on the device over the same primitives,
+    // used in place of the image's Dirichlet section when nodes is set
+    struct DirDev {
+        const void* nodes = nullptr;
+        const void* prims = nullptr;
+        const int32_t* orig = nullptr;
+        int32_t n_nodes = 0, n_prims = 0, stack = 0;
+    } dir_dev;
     wost::DevGeom devgeom() const;
+    // traversal stack entries a lane needs with the hierarchies in use
+    int32_t stack_need() const { return dir_dev.nodes && dir_dev.stack > stack_entries ? dir_dev.stack : stack_entries; }
 };
 
 namespace wost {

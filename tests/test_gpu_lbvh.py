@@ -189,3 +189,37 @@ def _pt_seg(x, a, b):
     e = b - a
     t = np.clip(np.dot(x - a, e) / max(np.dot(e, e), 1e-300), 0, 1)
     return np.linalg.norm(x - (a + t * e))
+
+
+@pytest.mark.parametrize("name,wpp", [("C2", 8), ("C4", 2)])
+def test_walks_over_a_gpu_built_dirichlet_hierarchy(W, name, wpp):
+    """The solve reading a GPU-built Dirichlet hierarchy (same primitives)
+    gives the same walks as over the host-built one: the closest distances
+    are identical, and where two primitives tie the closest point is their
+    shared point."""
+    from paper_2410_18944_amd.api import Lbvh
+    s = rounded({"C2": scenes.scene_c2, "C4": scenes.scene_c4}[name]())
+    pts = s.points[:: max(1, s.n_points // 4000)]
+    geom = W.Geometry.from_scene(s)
+    recs = _records(s.dim, s.verts, _dirichlet(s))
+    bv = Lbvh(s.dim, torch.as_tensor(recs, device="cuda").reshape(-1), leaf_size=4)
+    pb = W.Problem.from_scene(s)
+    out = {}
+    for which in ("host", "gpu"):
+        geom.use_dirichlet_lbvh(bv if which == "gpu" else None)
+        n = len(pts)
+        wv = torch.empty(n * wpp, dtype=torch.float32, device="cuda")
+        ws = torch.empty(n * wpp, dtype=torch.int32, device="cuda")
+        W.solve(geom, pb, torch.as_tensor(pts, dtype=torch.float32, device="cuda"), wpp, walk_value=wv,
+                walk_steps=ws)
+        q = geom.query(torch.as_tensor(pts, dtype=torch.float32, device="cuda"), silhouette=False)
+        torch.cuda.synchronize()
+        out[which] = (wv.double().cpu().numpy(), ws.cpu().numpy(), q["d_dir"].cpu().numpy())
+    geom.use_dirichlet_lbvh(None)
+    vh, sh, dh = out["host"]
+    vg, sg, dg = out["gpu"]
+    np.testing.assert_array_equal(dg, dh)
+    same = sg == sh
+    say("%s: walks with identical step counts over the GPU-built hierarchy %.5f" % (name, same.mean()))
+    assert same.mean() > 0.999
+    assert np.all(np.abs(vg - vh)[same] <= 1e-5 * np.maximum(1, np.abs(vh[same])))
