@@ -175,7 +175,28 @@ def test_upload_and_solve_reject_bad_arguments_without_launch(lib):
     assert L.wost_solve_wavefront_workspace_bytes(h, 100, 8) >= 100 * 8 * (4 + 20 + 4 * 26)  # 26 state words in 2D
     assert L.wost_set_wavefront_streams(3) < 0 and L.wost_set_wavefront_streams(0) < 0
     assert L.wost_set_wavefront_streams(2) == 0 and L.wost_set_wavefront_streams(1) == 0
+    # a GPU-built Dirichlet hierarchy must cover the same primitive count and
+    # fit the traversal stack; NULL nodes switch back (host-only checks)
+    n_dir = int((s.bc == 0).sum())
+    fake = C.c_void_p(4096)
+    assert L.wost_geom_use_dirichlet_lbvh(h, fake, 10, fake, fake, n_dir + 1, 5) == -1
+    assert L.wost_geom_use_dirichlet_lbvh(h, fake, 10, fake, fake, n_dir, 15) < 0
+    assert L.wost_geom_use_dirichlet_lbvh(h, fake, 10, fake, fake, n_dir, 14) == 0
+    assert L.wost_geom_use_dirichlet_lbvh(h, None, 0, None, None, 0, 0) == 0
     L.wost_geom_free(h)
+
+
+def test_lbvh_sizes_validate_and_scale(lib):
+    L = lib.load()
+    nb, pb, wb = C.c_int64(), C.c_int64(), C.c_int64()
+    assert L.wost_lbvh_sizes(4, 10, C.byref(nb), C.byref(pb), C.byref(wb)) < 0
+    assert L.wost_lbvh_sizes(3, 0, C.byref(nb), C.byref(pb), C.byref(wb)) < 0
+    assert L.wost_lbvh_sizes(3, 1, C.byref(nb), C.byref(pb), C.byref(wb)) == 0
+    assert nb.value == 7 * 16 and pb.value == 3 * 16
+    assert L.wost_lbvh_sizes(2, 1000, C.byref(nb), C.byref(pb), C.byref(wb)) == 0
+    # at most n - 1 four-wide nodes of 5 float4; one float4 per segment
+    assert nb.value == 999 * 5 * 16 and pb.value == 1000 * 16 and wb.value >= 1000 * 4 * 4
+    assert L.wost_lbvh_build(2, None, 1000, 4, None, None, None, None, None, None, 0, None) < 0
 
 
 def test_guide_create_validates_config(lib):
