@@ -474,7 +474,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             {
                 float x[D], r = 0.f, u1 = 0.f, u2 = 0.f;
                 SampleTrav q;
-                run_phase(L_step, n_step, (int32_t*)nullptr, dummy_n, lane, batch, witer[2],
+                run_phase(L_step, n_step, L_vis, n_vis, lane, batch, witer[2],
                     [&](int slot) {
                         const uint32_t g = base + slot;
 #pragma unroll
@@ -512,18 +512,8 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                         pv.f(F::NVAL, g) = green_ball<D>(r, rho) * hv * (ex.w / q.prob) * inv_alpha;
 #pragma unroll
                         for (int i = 0; i < D; ++i) pv.f(F::Z + i, g) = z[i];
-                        pv.i(F::STAT, g) = ST_VIS;
-                        return false;
+                        return true;
                     });
-            }
-            wave_sync();
-            // visibility candidates in slot order
-            for (int c0 = 0; c0 < N; c0 += kWave) {
-                const int li = c0 + lane;
-                const bool vis = pv.i(F::STAT, base + li) == ST_VIS;
-                const uint64_t m = __ballot(vis);
-                if (vis) L_vis[n_vis + (int)lane_prefix(m)] = li;
-                n_vis += __popcll(m);
             }
             wave_sync();
             if (n_vis > 0) {
@@ -551,7 +541,6 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                     [&](int slot) {
                         const uint32_t g = base + slot;
                         if (q.t.prim < 0) pv.f(F::CON, g) += pv.f(F::NVAL, g);
-                        pv.i(F::STAT, g) = ST_STEP;
                         return false;
                     });
                 wave_sync();

@@ -80,8 +80,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// ST_VIS: a stepping walk whose Neumann sample waits for its visibility ray
-enum : int { ST_EMPTY = 0, ST_ACTIVE = 1, ST_STEP = 2, ST_DONE = 3, ST_VIS = 4 };
+enum : int { ST_EMPTY = 0, ST_ACTIVE = 1, ST_STEP = 2, ST_DONE = 3 };
 
 template <int D>
 struct PoolField {
