@@ -45,13 +45,8 @@ class _Problem(C.Structure):
                 ("max_steps", C.c_int32), ("rr_start", C.c_int32), ("rr_q", C.c_double)]
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        build(force=True)
-    lib = C.CDLL(_LIB)
+def _bind(lib):
+    """Declare the argument and result types of the oracle's C entry points."""
     P = C.c_void_p
     dp = C.POINTER(C.c_double)
     lib.or_scene_create.restype = P
@@ -68,6 +63,8 @@ def _load():
     lib.or_walk_trace.restype = C.c_int32
     lib.or_walk_trace.argtypes = [P, C.POINTER(_Problem), dp, C.c_uint64, C.c_uint32, C.c_uint32,
                                   dp, dp, C.c_int32, dp, dp, C.POINTER(C.c_int32)]
+    lib.or_first_step.restype = C.c_int
+    lib.or_first_step.argtypes = [P, C.POINTER(_Problem), dp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int64, dp]
     lib.or_closest_dirichlet.argtypes = [P, dp, C.c_int64, dp, dp]
     lib.or_silhouette.argtypes = [P, dp, C.c_int64, C.POINTER(C.c_int64), dp]
     lib.or_ray_neumann.argtypes = [P, dp, dp, dp, C.c_int64, dp, C.POINTER(C.c_int64)]
@@ -78,8 +75,37 @@ def _load():
     lib.or_green_ball.argtypes = [C.c_int, C.c_double, C.c_double]
     lib.or_field_value.restype = C.c_double
     lib.or_field_value.argtypes = [C.c_int, C.c_int, dp, C.c_int, dp]
-    _lib = lib
     return lib
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    _lib = _bind(C.CDLL(_LIB))
+    return _lib
+
+
+def source_text() -> str:
+    """The oracle's C source (for tests that compile altered copies)."""
+    with open(_SRC) as fh:
+        return fh.read()
+
+
+def load_variant(src: str, directory: str, tag: str):
+    """Compile C source text ``src`` (an altered copy of the oracle, used by
+    the tests that check a pin fails under a planted mistake) into
+    ``directory`` and return its bound library handle, for
+    ``OracleScene(..., lib=...)``."""
+    c_path = os.path.join(directory, "oracle_%s.c" % tag)
+    so_path = os.path.join(directory, "liboracle_%s.so" % tag)
+    with open(c_path, "w") as fh:
+        fh.write(src)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-w", c_path, "-o", so_path, "-lm"],
+                   check=True)
+    return _bind(C.CDLL(so_path))
 
 
 def _ptr(a, t):
@@ -121,8 +147,9 @@ def field_value(field, dim, x):
 class OracleScene:
     """Exhaustive FP64 scene built from the seeded arrays of a ``scenes.Scene``."""
 
-    def __init__(self, scene, tau_rel=None):
-        lib = _load()
+    def __init__(self, scene, tau_rel=None, lib=None):
+        lib = lib if lib is not None else _load()
+        self._L = lib
         self.scene = scene
         self.dim = scene.dim
         self._v = np.ascontiguousarray(scene.verts, np.float64)
@@ -137,13 +164,13 @@ class OracleScene:
         self._keep = []
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib is not None:
-            _lib.or_scene_free(self.h)
+        if getattr(self, "h", None) and getattr(self, "_L", None) is not None:
+            self._L.or_scene_free(self.h)
             self.h = None
 
     @property
     def n_silhouette_candidates(self):
-        return _load().or_scene_n_silhouette_candidates(self.h)
+        return self._L.or_scene_n_silhouette_candidates(self.h)
 
     def _problem(self, eps=None, r_min=None, max_steps=None, rr_start=None, rr_q=None):
         s = self.scene
@@ -166,7 +193,7 @@ class OracleScene:
 
     def solve(self, points=None, wpp=None, seed=18944, walk_offset=0, per_walk=False,
               nthreads=0, point_ids=None, **problem_kw):
-        lib = _load()
+        lib = self._L
         pts = np.ascontiguousarray(self.scene.points if points is None else points, np.float64)
         n = pts.shape[0]
         wpp = self.scene.wpp if wpp is None else wpp
@@ -198,7 +225,7 @@ class OracleScene:
         return out
 
     def walk_trace(self, x0, p, j, seed=18944, cap=1 << 16, **problem_kw):
-        lib = _load()
+        lib = self._L
         pb = self._problem(**problem_kw)
         x0 = np.ascontiguousarray(x0, np.float64)
         c = np.zeros(cap)
@@ -212,12 +239,24 @@ class OracleScene:
         return {"c": c[:n], "w": w[:n], "value": val.value, "terminal": term.value,
                 "status": status.value}
 
+    def first_step(self, x0, n, p=0, j0=0, seed=18944, **problem_kw):
+        """Per walk, the first star's contribution N_0 + S_0 (0 if the walk
+        ends at once) for walks j0 .. j0 + n - 1 of point p started at x0."""
+        pb = self._problem(**problem_kw)
+        x0 = np.ascontiguousarray(x0, np.float64)
+        out = np.zeros(int(n))
+        rc = self._L.or_first_step(self.h, C.byref(pb), _ptr(x0, C.c_double), seed, p, j0, int(n),
+                                   _ptr(out, C.c_double))
+        if rc != 0:
+            raise RuntimeError("or_first_step failed")
+        return out
+
     def closest_dirichlet(self, x):
         x = np.ascontiguousarray(x, np.float64)
         n = x.shape[0]
         d = np.zeros(n)
         xb = np.zeros_like(x)
-        _load().or_closest_dirichlet(self.h, _ptr(x, C.c_double), n, _ptr(d, C.c_double),
+        self._L.or_closest_dirichlet(self.h, _ptr(x, C.c_double), n, _ptr(d, C.c_double),
                                      _ptr(xb, C.c_double))
         return d, xb
 
@@ -227,7 +266,7 @@ class OracleScene:
         x = np.ascontiguousarray(x, np.float64)
         d = np.zeros(x.shape[0])
         op = None if on_prim is None else np.ascontiguousarray(on_prim, np.int64)
-        _load().or_silhouette(self.h, _ptr(x, C.c_double), x.shape[0],
+        self._L.or_silhouette(self.h, _ptr(x, C.c_double), x.shape[0],
                               None if op is None else _ptr(op, C.c_int64), _ptr(d, C.c_double))
         return d
 
@@ -237,7 +276,7 @@ class OracleScene:
         tmax = np.ascontiguousarray(np.broadcast_to(tmax, (x.shape[0],)), np.float64)
         t = np.zeros(x.shape[0])
         pr = np.zeros(x.shape[0], np.int64)
-        _load().or_ray_neumann(self.h, _ptr(x, C.c_double), _ptr(nu, C.c_double),
+        self._L.or_ray_neumann(self.h, _ptr(x, C.c_double), _ptr(nu, C.c_double),
                                _ptr(tmax, C.c_double), x.shape[0], _ptr(t, C.c_double),
                                _ptr(pr, C.c_int64))
         return t, pr

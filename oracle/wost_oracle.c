@@ -640,6 +640,30 @@ int32_t or_walk_trace(const or_scene* s, const or_problem* pb, const double* x0,
     return tr.n;
 }
 
+/* Step-0 contribution N_0 + S_0 (Neumann and source terms of the first star)
+   of walks j = j0 .. j0 + n - 1 of point p started at x0; 0 where a walk ends
+   at step 0.  Its mean over walks estimates the first star's Green's-function
+   integrals of h and f (Sec. 3.2, equation "wost_estm"), which the tests
+   compare with quadrature. */
+int or_first_step(const or_scene* s, const or_problem* pb, const double* x0, uint64_t seed, uint32_t p,
+                  uint32_t j0, int64_t n, double* c0)
+{
+    if (!s || !pb || n < 0) return -1;
+    or_problem one = *pb;
+    one.max_steps = 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        or_rng g;
+        g.key[0] = (uint32_t)seed; g.key[1] = (uint32_t)(seed >> 32);
+        g.p = p; g.j = j0 + (uint32_t)i;
+        double c = 0.0, w = 0.0;
+        or_trace tr = {&c, &w, 1, 0};
+        walk_one(s, &one, x0, &g, &tr);
+        c0[i] = tr.n ? c : 0.0;
+    }
+    return 0;
+}
+
 /* batch query helpers for parity tests */
 void or_closest_dirichlet(const or_scene* s, const double* x, int64_t n, double* dist, double* xbar)
 {

@@ -403,6 +403,67 @@ def scene_cube_box(wpp: int = 64) -> Scene:
                  eps=1e-3, max_steps=4096, rr_start=128, rr_q=0.99, wpp=wpp)
 
 
+def scene_cube_neumann_face(wpp: int = 256) -> Scene:
+    """Cube [-1,1]^3 whose face y = +1 (two large triangles) is Neumann with
+    the outward derivative of u = x^2 - y^2 (h = -2 there); the other faces
+    are Dirichlet with g = u.  Large flat Neumann triangles make the
+    estimate sensitive to how points are drawn on them."""
+    s = scene_cube_box(wpp)
+    cen = s.verts[s.prims].mean(axis=1)
+    bc = (cen[:, 1] > 0.99).astype(np.uint8)
+    return dataclasses.replace(s, name="cube-neumann-face", bc=bc, h=_kind("x2_minus_y2"))
+
+
+def scene_cube_poisson(wpp: int = 256) -> Scene:
+    """Cube [-1,1]^3, all Dirichlet, manufactured u = |x|^2 (Laplacian u = 6)."""
+    s = scene_cube_box(wpp)
+    return dataclasses.replace(s, name="cube-poisson", g=_kind("r2"), f=(FIELD["const"], np.array([6.0])),
+                               u_exact=_kind("r2"))
+
+
+def scene_halfsphere_neumann(freq: int = 6, n_points: int = 64, wpp: int = 256, seed: int = 6) -> Scene:
+    """Geodesic unit sphere (20 freq^2 triangles): faces with centroid z > 0
+    Neumann with the outward derivative of u = x^2 - y^2, the others
+    Dirichlet with g = u; query points uniform in the ball r < 0.8."""
+    V, T = geodesic_sphere(freq)
+    cen = V[T].mean(axis=1)
+    bc = (cen[:, 2] > 0).astype(np.uint8)
+    rng = np.random.default_rng(seed)
+    Q = rng.uniform(-0.8, 0.8, size=(4 * n_points, 3))
+    Q = Q[np.linalg.norm(Q, axis=1) < 0.8][:n_points]
+    return Scene("halfsphere", 3, V, T, bc, np.ascontiguousarray(Q), g=_kind("x2_minus_y2"),
+                 h=_kind("x2_minus_y2"), f=_zero(), u_exact=_kind("x2_minus_y2"),
+                 eps=1e-3, max_steps=4096, rr_start=128, rr_q=0.99, wpp=wpp)
+
+
+def scene_sphere_neumann(freq: int = 6) -> Scene:
+    """Geodesic unit sphere, every face Neumann (a convex closed surface)."""
+    V, T = geodesic_sphere(freq)
+    return Scene("sphere-neumann", 3, V, T, np.ones(T.shape[0], np.uint8), np.zeros((1, 3)),
+                 g=_zero(), h=_zero(), f=_zero(), u_exact=None)
+
+
+def scene_l_prism() -> Scene:
+    """L-shaped prism: the square [-1,1]^2 without the quadrant x > 0, y < 0,
+    extruded over z in [-1, 1]; every face Neumann.  Its one reflex edge is
+    the segment x = y = 0, |z| <= 1.  Side quads are split along a diagonal,
+    the end caps fanned from the reflex corner."""
+    L2 = np.array([[-1, -1], [0, -1], [0, 0], [1, 0], [1, 1], [-1, 1]], float)   # counter-clockwise
+    n = L2.shape[0]
+    V = np.concatenate([np.c_[L2, -np.ones(n)], np.c_[L2, np.ones(n)]])
+    T = []
+    for i in range(n):
+        j = (i + 1) % n
+        a, b, c, d = i, j, n + j, n + i           # side quad, counter-clockwise seen from outside
+        T += [(a, b, c), (a, c, d)]
+    for k in (3, 4, 5, 0):                         # caps: fan from the reflex corner (vertex 2)
+        T.append((n + 2, n + k, n + (k + 1) % n))  # top, outward +z
+        T.append((2, (k + 1) % n, k))              # bottom, outward -z
+    T = np.asarray(T, np.int32)
+    return Scene("l-prism", 3, V, T, np.ones(T.shape[0], np.uint8), np.zeros((1, 3)),
+                 g=_zero(), h=_zero(), f=_zero(), u_exact=None)
+
+
 SCENES = {
     "C1": scene_c1,
     "C1-poisson": scene_c1_poisson,
@@ -411,6 +472,9 @@ SCENES = {
     "C4": scene_c4,
     "C5": scene_c5,
     "cube": scene_cube_box,
+    "cube-neumann-face": scene_cube_neumann_face,
+    "cube-poisson": scene_cube_poisson,
+    "halfsphere": scene_halfsphere_neumann,
 }
 
 
