@@ -340,6 +340,41 @@ def test_grid_weights_partition_unity_and_hash_range():
         assert np.all(w >= 0) and idx.min() >= 0 and idx.max() < cfg.T
 
 
+def _hash_kat():
+    import os
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "hash_grid_kat.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                v = [int(t) for t in line.split()]
+                rows[v[0]] = v[1:]
+    return rows
+
+
+def _check_hash_kat(primes=None, monkeypatch=None):
+    if primes is not None:
+        monkeypatch.setattr(G, "HASH_PRIMES", primes)
+    cfg = G.GuideConfig(dim=3, levels=16, feats=2, log2_T=19, n_min=16, n_max=512, aabb_lo=(0.0,) * 3,
+                        aabb_hi=(1.0,) * 3)
+    assert [cfg.resolution(l) for l in range(16)] == [16, 20, 25, 32, 40, 50, 64, 80, 101, 128, 161, 203, 256,
+                                                       322, 406, 512]
+    out = G.grid_corners(cfg, np.array([[0.301, 0.551, 0.901]]))
+    for level, want in _hash_kat().items():
+        assert out[level][0][0].tolist() == want, (level, out[level][0][0].tolist(), want)
+
+
+def test_hash_grid_indices_match_hand_computed_values():
+    """Dense and hashed cell indices of the 3D guide's grid against values
+    worked out by hand from the definitions (tests/golden/hash_grid_kat.txt)."""
+    _check_hash_kat()
+
+
+@pytest.mark.parametrize("primes", [(1, 2654435761, 805459863), (1, 805459861, 2654435761), (2654435761, 1, 805459861)])
+def test_hash_known_answers_fail_under_a_wrong_prime(monkeypatch, primes):
+    with pytest.raises(AssertionError):
+        _check_hash_kat(primes, monkeypatch)
+
+
 def _train_batch(cfg, rng, n=64):
     d = cfg.dim
     x = rng.uniform(-0.9, 0.9, size=(n, d))
