@@ -1,6 +1,7 @@
 """Build the gfx950 library ``libwost.so`` in-tree with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -31,18 +32,27 @@ def build(verbose: bool = False) -> str:
     inc = ["-I", os.path.join(HERE, "..", "include")]
     objs = []
     tag = "%d" % os.getpid()
+
+    def compile_one(src):
+        obj = os.path.join(CSRC, src + ".o" + tag)
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *EXTRA.get(src, []), *inc, "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        return src, obj, subprocess.run(cmd, capture_output=True, text=True)
+
     try:
-        for src in srcs:
-            obj = os.path.join(CSRC, src + ".o" + tag)
-            cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *EXTRA.get(src, []), *inc, "-c",
-                   os.path.join(CSRC, src), "-o", obj]
-            res = subprocess.run(cmd, capture_output=True, text=True)
+        # the sources compile independently: one hipcc process each
+        jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(compile_one, srcs))
+        for src, obj, res in results:
+            if res.returncode == 0:
+                objs.append(obj)
+        for src, obj, res in results:
             if res.returncode != 0:
                 sys.stderr.write(res.stdout + res.stderr)
                 raise RuntimeError("hipcc failed compiling %s" % src)
             if verbose:
                 sys.stderr.write(res.stderr)
-            objs.append(obj)
         tmp = LIB + ".tmp" + tag
         res = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
                              capture_output=True, text=True)
