@@ -357,6 +357,23 @@ int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin,
                           const wost_adam* opt, float* loss_out, void* workspace, int64_t ws_bytes,
                           void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * training step as wost_guide_train_step, with its workspace taken from a
+ * library-owned device array of WOST_NOALLOC_SCRATCH_BYTES instead of a
+ * caller buffer.  The call itself allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine); each device holds its own copy of the array
+ * from library load until the process ends.  Every call on one device uses
+ * that device's copy, so calls that overlap on a device (other streams, other
+ * threads) race and must be ordered by the caller.  WOST_ESIZE if `count`
+ * records need more workspace than the array holds
+ * (wost_guide_train_workspace_bytes(g, count) > WOST_NOALLOC_SCRATCH_BYTES;
+ * 2^18 records fit for the 2D and 3D guides of the benchmark scenes).  Other
+ * arguments and errors as wost_guide_train_step. */
+#define WOST_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int wost_guide_train_step_noalloc(wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
+                                  const wost_adam* opt, float* loss_out, void* stream);
+
 /* ------------------------------------------------------------ GPU hierarchy build
  * Linear BVH built on the GPU (Karras 2012; the paper's query library uses a
  * linear BVH, Sec. 5.3) over a primitive set for closest-point queries, in

@@ -22,6 +22,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "guide_device.h"
 #include "guide_internal.h"
@@ -893,4 +894,63 @@ extern "C" int wost_guide_train_step(wost_guide* g, const wost_records* rec, int
                           1.f / (float)count, g->grad, workspace, ws_bytes, true, s);
     if (rc != WOST_OK) return rc;
     return wost_guide_adam_step(g, opt, stream);
+}
+
+// ---------------------------------------------------------------- allocation-free training step
+namespace wost {
+
+// Workspace of wost_guide_train_step_noalloc: the per-workgroup weight-gradient
+// partials and the per-record coarse-level staging of one training step.  It
+// is a device-side array; its name in host code is not a device address, so
+// the host uses the address hipGetSymbolAddress returns for the current
+// device.  Every device that loads the library holds its own copy until the
+// process ends, and every call on a device reuses that device's copy (the
+// kernels overwrite what they read: each workgroup clears its own partial row
+// and every record writes its staging entries).
+static __device__ __align__(256) unsigned char scratch[WOST_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+static void* g_scratch_addr[kMaxScratchDevices];
+static std::mutex g_scratch_mu;
+
+// address of `scratch` on the current device, looked up once per device
+static int scratch_address(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) {
+        set_error("wost_guide_train_step_noalloc: no usable current device (%d)", dev);
+        return WOST_EHIP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("wost_guide_train_step_noalloc: scratch address on device %d: %s", dev, hipGetErrorString(e));
+            return WOST_EHIP;
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return WOST_OK;
+}
+
+}  // namespace wost
+
+extern "C" int wost_guide_train_step_noalloc(wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
+                                             const wost_adam* opt, float* loss_out, void* stream)
+{
+    if (!g || !opt) { set_error("wost_guide_train_step_noalloc: NULL argument"); return WOST_EINVAL; }
+    if (count < 0) { set_error("wost_guide_train_step_noalloc: negative record count"); return WOST_EINVAL; }
+    const int64_t need = wost_guide_train_workspace_bytes(g, count);
+    if (need < 0 || need > (int64_t)WOST_NOALLOC_SCRATCH_BYTES) {
+        set_error("wost_guide_train_step_noalloc: %lld records need %lld bytes of workspace, above the %lld-byte "
+                  "library scratch; use fewer records per call or wost_guide_train_step",
+                  (long long)count, (long long)need, (long long)WOST_NOALLOC_SCRATCH_BYTES);
+        return WOST_ESIZE;
+    }
+    void* ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc != WOST_OK) return rc;
+    return wost_guide_train_step(g, rec, begin, count, opt, loss_out, ws, (int64_t)WOST_NOALLOC_SCRATCH_BYTES, stream);
 }

@@ -140,6 +140,16 @@ class Guide:
                                                _ptr(loss_out), _ptr(ws), ws.numel(), _stream()),
                 "wost_guide_train_step")
 
+    def train_step_noalloc(self, records, begin, count, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8, e_mis=0.2,
+                           loss_out=None):
+        """``train_step`` through the allocation-free entry point (workspace
+        in the library's own device array; nothing is allocated)."""
+        opt = L.wost_adam(lr, beta1, beta2, eps, e_mis)
+        rec = records.to_c()
+        L.check(L.load().wost_guide_train_step_noalloc(self.h, C.byref(rec), int(begin), int(count), C.byref(opt),
+                                                       _ptr(loss_out), _stream()),
+                "wost_guide_train_step_noalloc")
+
     def sample(self, pts, normals=None, sampling="mis_learned", c_fixed=0.5, seed=18944, walk_index=0):
         pts = pts.contiguous()
         n = pts.shape[0]
