@@ -385,6 +385,35 @@ def scene_c5(freq: int = 224, n_random: int = 1 << 20, **kw) -> Scene:
     return scene_3d("C5", freq, n_random=n_random, with_source=True, **kw)
 
 
+def scene_c5_manufactured(n_random: int = 8192, freq: int = 224, **kw) -> Scene:
+    """The C5 geometry (noise-displaced sphere with three holes, z > 0 of the
+    outer surface Neumann) with the manufactured solution u = |x|^2: source
+    Laplacian u = 6, Dirichlet g = u, Neumann data its outward derivative;
+    n_random uniform interior query points."""
+    s = scene_3d("C5-manufactured", freq, n_random=n_random, **kw)
+    return dataclasses.replace(s, g=_kind("r2"), h=_kind("r2"), f=(FIELD["const"], np.array([6.0])),
+                               u_exact=_kind("r2"))
+
+
+def scene_sphere_sources(freq: int = 6, n_points: int = 64, wpp: int = 64, seed: int = 12) -> Scene:
+    """Geodesic unit sphere, all Dirichlet with g = x^2 - y^2, and a source
+    of 16 seeded Gaussian bumps (amplitudes U(0.5, 2), widths U(0.05, 0.2),
+    centres in the ball r < 0.7) -- the source recipe of the 1M-triangle
+    Poisson workload on a mesh small enough for brute-force queries."""
+    V, T = geodesic_sphere(freq)
+    rng = np.random.default_rng(seed)
+    rows = []
+    while len(rows) < 16:
+        c = rng.uniform(-0.7, 0.7, size=3)
+        if np.linalg.norm(c) < 0.7:
+            rows.append([rng.uniform(0.5, 2.0), rng.uniform(0.05, 0.2), *c])
+    Q = rng.uniform(-0.8, 0.8, size=(8 * n_points, 3))
+    Q = Q[np.linalg.norm(Q, axis=1) < 0.8][:n_points]
+    return Scene("sphere-sources", 3, V, T, np.zeros(T.shape[0], np.uint8), np.ascontiguousarray(Q),
+                 g=_kind("x2_minus_y2"), h=_zero(), f=(FIELD["gauss_sum"], np.asarray(rows, float)),
+                 u_exact=None, eps=1e-3, max_steps=4096, rr_start=128, rr_q=0.99, wpp=wpp)
+
+
 def scene_cube_box(wpp: int = 64) -> Scene:
     """Axis-aligned unit cube [-1,1]^3 (12 triangles), all Dirichlet, u = x^2 - y^2."""
     v = np.array([[x, y, z] for x in (-1, 1) for y in (-1, 1) for z in (-1, 1)], float)
@@ -475,6 +504,8 @@ SCENES = {
     "cube-neumann-face": scene_cube_neumann_face,
     "cube-poisson": scene_cube_poisson,
     "halfsphere": scene_halfsphere_neumann,
+    "C5-manufactured": scene_c5_manufactured,
+    "sphere-sources": scene_sphere_sources,
 }
 
 
