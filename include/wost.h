@@ -133,6 +133,26 @@ int wost_query(const wost_geom* geom, const float* pts, int64_t n, const int32_t
                float* d_dir, float* xbar, float* d_sil, const float* ray_dir, const float* ray_tmax,
                float* ray_t, int32_t* ray_prim, void* stream);
 
+/* The Neumann-sample step of a walk for given states (for parity tests of
+ * the Neumann contribution, Sec. 3.2 eq. wost_estm): one primitive meeting
+ * the ball B(x, r) is chosen by a descent of the Neumann hierarchy (children
+ * in proportion to their subtree measure, then a leaf primitive in proportion
+ * to its measure among those meeting the ball), a point z uniform on it, and
+ * z is accepted if |z - x| < r, it does not lie behind the walker's tangent
+ * plane (points on a Neumann primitive), and it is visible from the walker's
+ * ray origin.  The walk then scores G_r(|z - x|) h(z) |q| / prob / alpha.
+ *   pts       device [n][dim]; on_prim device [n] or NULL (as wost_query)
+ *   radius    device [n] star radii r
+ *   uniforms  device [n][3] numbers in [0, 1): the descent's uniform and the
+ *             two that place z on the primitive
+ *   prim      device [n] caller index of the chosen primitive (-1: none)
+ *   prob      device [n] probability with which it was chosen
+ *   z         device [n][dim] the point (+inf if none)
+ *   accepted  device [n] 1 if z passed the checks above, else 0 */
+int wost_neumann_sample(const wost_geom* geom, const float* pts, int64_t n, const int32_t* on_prim,
+                        const float* radius, const float* uniforms, int32_t* prim, float* prob, float* z,
+                        int32_t* accepted, void* stream);
+
 /* ------------------------------------------------------------ problem + solve */
 #define WOST_SAMPLING_UNIFORM 0      /* original WoSt: uniform directions (c = 0)       */
 #define WOST_SAMPLING_MIS_LEARNED 1  /* MIS with the guide's learned c(x) (Sec. 4.4)    */

@@ -394,8 +394,11 @@ double or_ray_neumann_one(const or_scene* s, const double* x, const double* nu, 
     return bq >= 0 ? best : INFINITY;
 }
 
-/* no Neumann primitive (other than `skip`) crosses the open segment (x, z) */
-static int visible(const or_scene* s, const double* x, const double* z, int64_t skip)
+/* no Neumann primitive (other than `skip` and `skip2`) crosses the open
+   segment (x, z).  A point z on a primitive is tested with that primitive
+   skipped: a flat primitive meets the segment to one of its points only at
+   that point, so it can never block it. */
+static int visible(const or_scene* s, const double* x, const double* z, int64_t skip, int64_t skip2)
 {
     const int d = s->dim;
     double nu[3], len = 0;
@@ -404,7 +407,7 @@ static int visible(const or_scene* s, const double* x, const double* z, int64_t 
     if (len == 0) return 1;
     for (int i = 0; i < d; ++i) nu[i] /= len;
     for (int64_t q = 0; q < s->n_prims; ++q) {
-        if (!s->bc[q] || q == skip) continue;
+        if (!s->bc[q] || q == skip || q == skip2) continue;
         double t = ray_prim(s, q, x, nu);
         if (t > s->tau && t < len - s->tau) return 0;
     }
@@ -524,7 +527,7 @@ static or_walk_result walk_one(const or_scene* s, const or_problem* pb, const do
                 rho = sqrt(rho);
                 int ok = rho < r && rho > 0.0;
                 if (ok && onN && dot(d, dz, n_in) < -s->tau) ok = 0;
-                if (ok && !visible(s, x, z, onN ? on_prim : -1)) ok = 0;
+                if (ok && !visible(s, x, z, onN ? on_prim : -1, sel)) ok = 0;
                 if (ok) {
                     double hv = neumann_value(&pb->h, d, z, s->n_out + sel * d);
                     contrib += green_ball(d, r, rho) * hv * A / alpha;
@@ -549,7 +552,7 @@ static or_walk_result walk_one(const or_scene* s, const or_problem* pb, const do
             for (int i = 0; i < d; ++i) y[i] = x[i] + sr * r * nu2[i];
             int ok = sr > 0.0;
             if (ok && onN && dot(d, nu2, n_in) <= 0.0) ok = 0;
-            if (ok && !visible(s, x, y, onN ? on_prim : -1)) ok = 0;
+            if (ok && !visible(s, x, y, onN ? on_prim : -1, -1)) ok = 0;
             if (ok) contrib += -(r * r / (2.0 * d)) * field_value(&pb->f, d, y) / alpha;
         }
         U += T * contrib;

@@ -66,6 +66,7 @@ SIGNATURES = {
     "wost_geom_prim_index": (_I64, [_P, _I32]),
     "wost_geom_free": (None, [_P]),
     "wost_query": (_I, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "wost_neumann_sample": (_I, [_P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P]),
     "wost_solve_workspace_bytes": (_I64, [_P, _I64, _I32]),
     "wost_solve": (_I, [_P, C.POINTER(wost_problem), _P, _I64, _I32, _U64, _U64, _P, _P, _P, _P, _P, _P,
                         C.POINTER(wost_records), _P, _I64, _P, _P]),

@@ -96,6 +96,22 @@ class Geometry:
                                                      _ptr(bv.orig), bv.n, bv.levels), "wost_geom_use_dirichlet_lbvh")
         self._dir_lbvh = bv      # keeps the buffers alive while in use
 
+    def neumann_sample(self, pts, radius, uniforms, on_prim=None):
+        """The walk's Neumann-sample step at given states (wost_neumann_sample):
+        returns dict(prim, prob, z, accepted) as tensors."""
+        lib = L.load()
+        pts = pts.contiguous()
+        n = pts.shape[0]
+        dev = pts.device
+        out = dict(prim=torch.empty(n, dtype=torch.int32, device=dev), prob=torch.empty(n, dtype=torch.float32, device=dev),
+                   z=torch.empty(n, self.dim, dtype=torch.float32, device=dev),
+                   accepted=torch.empty(n, dtype=torch.int32, device=dev))
+        op = on_prim.contiguous() if on_prim is not None else None
+        L.check(lib.wost_neumann_sample(self.h, _ptr(pts), n, _ptr(op), _ptr(radius.contiguous()),
+                                        _ptr(uniforms.contiguous()), _ptr(out["prim"]), _ptr(out["prob"]),
+                                        _ptr(out["z"]), _ptr(out["accepted"]), _stream()), "wost_neumann_sample")
+        return out
+
     def query(self, pts, dirichlet=True, silhouette=True, ray_dir=None, ray_tmax=None, on_prim=None):
         lib = L.load()
         pts = pts.contiguous()

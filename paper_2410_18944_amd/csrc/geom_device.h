@@ -641,12 +641,16 @@ __device__ __forceinline__ bool ray_neumann_step(const DevBvh& b, const float* x
     return !trav_next4(kk[0], kk[1], kk[2], kk[3], n.ref, q.t.best, q.t, st);
 }
 
-// ---- visibility: does a Neumann primitive other than `skip` cross the ray
-// x + t nu (unit nu) at t in (t_lo, t_hi)?  Any-hit: finishes at the first
-// blocker, with q.t.prim >= 0; q.t.best holds t_hi.
+// ---- visibility: does a Neumann primitive other than `skip` and `skip2`
+// cross the ray x + t nu (unit nu) at t in (t_lo, t_hi)?  Any-hit: finishes
+// at the first blocker, with q.t.prim >= 0; q.t.best holds t_hi.  A ray
+// toward a point on a primitive skips that primitive: a flat primitive meets
+// the segment to one of its points only there, and at the grazing angles of
+// rays along the boundary the FP32 crossing parameter of the target's own
+// primitive can land well short of the end of the ray.
 template <int D, class S>
 __device__ __forceinline__ bool visible_neumann_step(const DevBvh& b, const float* x, const float* nu, float t_lo,
-                                                     int skip, RayTrav<D>& q, const LdsStack& st, S* s)
+                                                     int skip, int skip2, RayTrav<D>& q, const LdsStack& st, S* s)
 {
     if (q.t.node < 0) return true;
     const RaySetup<D> ry(x, nu);
@@ -665,7 +669,7 @@ __device__ __forceinline__ bool visible_neumann_step(const DevBvh& b, const floa
         const int r = comp(n.ref, k);
         const int f = leaf_first(r), c = leaf_count(r);
         for (int j = f; j < f + c; ++j) {
-            if (j == skip) continue;
+            if (j == skip || j == skip2) continue;
             Prim<D> pr; pr.load(b.prims, j); stat_prim(s);
             const float t = pr.ray(ry);
             if (t > t_lo && t < tmax) { q.t.prim = j; q.t.node = -1; return true; }
@@ -809,11 +813,11 @@ __device__ float ray_neumann(const DevBvh& b, const float* x, const float* nu, f
 
 template <int D, class S = NoStat>
 __device__ bool visible_neumann(const DevBvh& b, const float* x, const float* nu, float t_lo, float t_hi, int skip,
-                                const LdsStack& st, S* s = nullptr)
+                                int skip2, const LdsStack& st, S* s = nullptr)
 {
     RayTrav<D> q;
     ray_begin<D>(b, nu, t_hi, q);
-    while (!visible_neumann_step<D>(b, x, nu, t_lo, skip, q, st, s)) {}
+    while (!visible_neumann_step<D>(b, x, nu, t_lo, skip, skip2, q, st, s)) {}
     return q.t.prim < 0;
 }
 

@@ -512,18 +512,22 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                         pv.f(F::NVAL, g) = green_ball<D>(r, rho) * hv * (ex.w / q.prob) * inv_alpha;
 #pragma unroll
                         for (int i = 0; i < D; ++i) pv.f(F::Z + i, g) = z[i];
+                        // the sample's primitive, for its visibility ray (the
+                        // hit field is free until the first-hit phase)
+                        pv.i(F::HIT, g) = q.prim;
                         return true;
                     });
             }
             wave_sync();
             if (n_vis > 0) {
                 float xo[D], dn[D];
-                int onp = -1;
+                int onp = -1, zp = -1;
                 RayTrav<D> q;
                 run_phase(L_vis, n_vis, (int32_t*)nullptr, dummy_n, lane, batch, witer[3],
                     [&](int slot) {
                         const uint32_t g = base + slot;
                         onp = pv.i(F::ONP, g);
+                        zp = pv.i(F::HIT, g);
                         float l2 = 0.f;
 #pragma unroll
                         for (int i = 0; i < D; ++i) {
@@ -537,7 +541,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                         for (int i = 0; i < D; ++i) dn[i] /= len;
                         ray_begin<D>(G.neu, dn, len - G.tau, q);
                     },
-                    [&]() { return visible_neumann_step<D>(G.neu, xo, dn, 0.f, onp, q, st, &sq[3]); },
+                    [&]() { return visible_neumann_step<D>(G.neu, xo, dn, 0.f, onp, zp, q, st, &sq[3]); },
                     [&](int slot) {
                         const uint32_t g = base + slot;
                         if (q.t.prim < 0) pv.f(F::CON, g) += pv.f(F::NVAL, g);
@@ -626,7 +630,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                         for (int i = 0; i < D; ++i) dy[i] /= len;
                         ray_begin<D>(G.neu, dy, len, q);
                     },
-                    [&]() { return visible_neumann_step<D>(G.neu, xo, dy, 0.f, onp, q, st, &sq[4]); },
+                    [&]() { return visible_neumann_step<D>(G.neu, xo, dy, 0.f, onp, -1, q, st, &sq[4]); },
                     [&](int slot) {
                         if (q.t.prim < 0) {
                             const uint32_t g = base + slot;
@@ -802,6 +806,74 @@ __global__ __launch_bounds__(64) void query_kernel(const DevGeom G, const float*
         ray_t[i] = t;
         if (ray_prim) ray_prim[i] = hp >= 0 ? G.neu.orig[hp] : -1;
     }
+}
+
+// The walk's Neumann-sample step for given states (for parity tests): the
+// descent choosing one primitive meeting B(x, r), the point on it, the
+// in-ball and facing checks, and the visibility ray from the walker's origin
+// -- the same steps, in the same order and precision, as the Neumann phase of
+// walk_body.
+template <int D>
+__global__ __launch_bounds__(64) void neumann_sample_kernel(const DevGeom G, const float* pts, int64_t n,
+                                                            const int32_t* on_prim, const float* radius,
+                                                            const float* uni, int32_t* prim_out, float* prob_out,
+                                                            float* z_out, int32_t* ok_out)
+{
+    __shared__ uint2 s_stack[kMaxStack * kWave];
+    const int lane = threadIdx.x;
+    const LdsStack st{&s_stack[lane]};
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
+    if (i >= n) return;
+    float x[D], nin[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) { x[c] = pts[i * D + c]; nin[c] = 0.f; }
+    const int32_t qc = on_prim ? on_prim[i] : -1;
+    const int onp = qc >= 0 && qc < G.n_caller && G.neu_id ? G.neu_id[qc] : -1;
+    if (onp >= 0) {
+        const float4 ex = G.neu.pextra[onp];
+#pragma unroll
+        for (int c = 0; c < D; ++c) nin[c] = -(c == 0 ? ex.x : (c == 1 ? ex.y : ex.z));
+    }
+    const float r = radius[i];
+    SampleTrav q;
+    sample_begin(G.neu, uni[i * 3], q);
+    while (!sample_neumann_step<D>(G.neu, x, r, q, (NoStat*)nullptr)) {}
+    prim_out[i] = q.prim >= 0 ? G.neu.orig[q.prim] : -1;
+    prob_out[i] = q.prob;
+    int ok = 0;
+    float z[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) z[c] = INFINITY;
+    if (q.prim >= 0 && q.prob > 0.f) {
+        Prim<D> pr;
+        pr.load(G.neu.prims, q.prim);
+        float dz[D], rho2 = 0.f;
+        pr.point(uni[i * 3 + 1], uni[i * 3 + 2], z);
+#pragma unroll
+        for (int c = 0; c < D; ++c) { dz[c] = z[c] - x[c]; rho2 = fmaf(dz[c], dz[c], rho2); }
+        const float rho = sqrtf(rho2);
+        bool acc = rho < r && rho > 0.f;
+        if (acc && onp >= 0 && dot<D>(dz, nin) < -G.tau) acc = false;
+        if (acc) {
+            float xo[D], dn[D], l2 = 0.f;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                xo[c] = onp >= 0 ? fmaf(G.tau, nin[c], x[c]) : x[c];
+                dn[c] = z[c] - xo[c];
+                l2 = fmaf(dn[c], dn[c], l2);
+            }
+            const float len = sqrtf(l2);
+#pragma unroll
+            for (int c = 0; c < D; ++c) dn[c] /= len;
+            RayTrav<D> rq;
+            ray_begin<D>(G.neu, dn, len - G.tau, rq);
+            while (!visible_neumann_step<D>(G.neu, xo, dn, 0.f, onp, q.prim, rq, st, (NoStat*)nullptr)) {}
+            ok = rq.t.prim < 0 ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) z_out[i * D + c] = z[c];
+    ok_out[i] = ok;
 }
 
 static int g_num_cu = 0;
@@ -1076,6 +1148,32 @@ extern "C" int wost_solve(const wost_geom* geom, const wost_problem* pb, const f
     launch_reduce_points(P, sum, sum_sq, count, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("wost_solve: launch failed: %s", hipGetErrorString(e)); return WOST_EHIP; }
+    return WOST_OK;
+}
+
+extern "C" int wost_neumann_sample(const wost_geom* geom, const float* pts, int64_t n, const int32_t* on_prim,
+                                   const float* radius, const float* uniforms, int32_t* prim, float* prob, float* z,
+                                   int32_t* accepted, void* stream)
+{
+    if (!geom) { set_error("wost_neumann_sample: NULL geometry"); return WOST_EINVAL; }
+    if (!geom->dev) { set_error("wost_neumann_sample: geometry not uploaded"); return WOST_ESTATE; }
+    if (n < 0) { set_error("wost_neumann_sample: n < 0"); return WOST_EINVAL; }
+    if (n == 0) return WOST_OK;
+    if (!pts || !radius || !uniforms || !prim || !prob || !z || !accepted) {
+        set_error("wost_neumann_sample: NULL buffer");
+        return WOST_EINVAL;
+    }
+    const DevGeom G = geom->devgeom();
+    hipStream_t s = (hipStream_t)stream;
+    const int grid = (int)((n + 63) / 64);
+    if (geom->dim == 2)
+        hipLaunchKernelGGL(neumann_sample_kernel<2>, dim3(grid), dim3(64), 0, s, G, pts, n, on_prim, radius, uniforms,
+                           prim, prob, z, accepted);
+    else
+        hipLaunchKernelGGL(neumann_sample_kernel<3>, dim3(grid), dim3(64), 0, s, G, pts, n, on_prim, radius, uniforms,
+                           prim, prob, z, accepted);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error("wost_neumann_sample: launch failed: %s", hipGetErrorString(e)); return WOST_EHIP; }
     return WOST_OK;
 }
 

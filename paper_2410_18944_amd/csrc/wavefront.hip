@@ -281,6 +281,9 @@ __global__ __launch_bounds__(64) void wf_neumann(const WalkParams P, const WfQue
                     pv.f(F::NVAL, g) = green_ball<D>(r, rho) * hv * (ex.w / prob) * inv_alpha;
 #pragma unroll
                     for (int i = 0; i < D; ++i) pv.f(F::Z + i, g) = z[i];
+                    // the sample's primitive, for its visibility ray (the hit
+                    // field is free until the first-hit stage)
+                    pv.i(F::HIT, g) = prim;
                     app = true;
                 }
             }
@@ -313,7 +316,8 @@ __global__ __launch_bounds__(64) void wf_neumann_visibility(const WalkParams P, 
         const float len = sqrtf(l2);
 #pragma unroll
         for (int i = 0; i < D; ++i) dn[i] /= len;
-        if (visible_neumann<D>(G.neu, xo, dn, 0.f, len - G.tau, onp, st)) pv.f(F::CON, g) += pv.f(F::NVAL, g);
+        if (visible_neumann<D>(G.neu, xo, dn, 0.f, len - G.tau, onp, pv.i(F::HIT, g), st))
+            pv.f(F::CON, g) += pv.f(F::NVAL, g);
     }
 }
 
@@ -401,7 +405,7 @@ __global__ __launch_bounds__(64) void wf_source_visibility(const WalkParams P, c
         const float len = sqrtf(l2);
 #pragma unroll
         for (int i = 0; i < D; ++i) dy[i] /= len;
-        if (visible_neumann<D>(G.neu, xo, dy, 0.f, len, onp, st)) pv.f(F::CON, g) -= pv.f(F::SVAL, g);
+        if (visible_neumann<D>(G.neu, xo, dy, 0.f, len, onp, -1, st)) pv.f(F::CON, g) -= pv.f(F::SVAL, g);
     }
 }
 
