@@ -355,23 +355,36 @@ def test_loss_and_backward_match_fp64_reference(W, dim, K, reflected):
     with torch.no_grad():
         y = G.forward(rcfg, p16, batch[0], round_inputs=True)
         ref_loss = G.loss_per_sample(rcfg, y, *batch[1:], reflected=reflected).numpy()
+    # Both networks round every layer input to FP16.  Where a value lies
+    # within FP32 rounding of an FP16 rounding boundary, the GPU (FP32
+    # accumulation) and the reference (FP64) may round it to different
+    # neighbours, both correct; such a record's outputs then differ by up to
+    # about one FP16 step of an input (~1e-3 of the output scale), and its
+    # loss gradient, steep in the mean directions of a fresh network, by more.
+    # Every record is held to that bound; the records where the two forward
+    # passes agree to FP32 rounding (98-99% of them) are compared tightly.
+    y_gpu = g.infer(_t(batch[0])).double().cpu().numpy()
+    yscale = np.sqrt(np.mean(y.numpy() ** 2))
+    yerr = np.abs(y_gpu - y.numpy()).max(1) / yscale
+    same = yerr < 1e-5
+    say("forward: %d of %d records agree to FP32 rounding, max err elsewhere %.2e"
+        % (same.sum(), n, yerr.max()))
+    assert yerr.max() < 2e-3 and same.mean() > 0.97
     lerr = np.abs(loss - ref_loss) / (np.abs(ref_loss) + np.mean(np.abs(ref_loss)))
-    say("loss rel err max %.2e" % lerr.max())
-    assert np.percentile(lerr, 99) < 2e-3
-    # gradient of the mean loss via the autograd Function
+    say("loss rel err max %.2e (records with equal rounding: %.2e)" % (lerr.max(), lerr[same].max()))
+    assert lerr.max() < 2e-3 and lerr[same].max() < 1e-5
+    # gradient of the loss over those records via the autograd Function
+    mask = torch.as_tensor(same, dtype=torch.float32, device="cuda")
     params = g.master.clone().requires_grad_(True)
     lv = W.GuideLoss.apply(params, g, rec, 0, n, 0.2)
-    lv.mean().backward()
+    ((lv * mask).sum() / n).backward()
     grad = params.grad.double().cpu().numpy()
-    # FP64 reference gradient of the same loss at the network state the GPU
-    # computed: the per-record loss gradient is taken at the GPU's outputs
-    # (it is steep in kappa, so ~1e-3 forward differences would dominate),
-    # then back-propagated through the network in float64
-    y_gpu = torch.as_tensor(g.infer(_t(batch[0])).double().cpu().numpy())
+    # FP64 reference gradient of the same loss through the reference's own
+    # forward pass (FP16-rounded layer inputs); no GPU value enters it
     p = torch.tensor(p16, dtype=torch.float64, requires_grad=True)
     y_ref = G.forward(rcfg, p, batch[0], round_inputs=True)
-    y_at = y_ref + (y_gpu - y_ref).detach()
-    G.loss_per_sample(rcfg, y_at, *batch[1:], reflected=reflected).mean().backward()
+    lref = G.loss_per_sample(rcfg, y_ref, *batch[1:], reflected=reflected)
+    ((lref * torch.as_tensor(same, dtype=torch.float64)).sum() / n).backward()
     ref_grad = p.grad.numpy()
     rel = np.linalg.norm(grad - ref_grad) / np.linalg.norm(ref_grad)
     ng = rcfg.n_grid_params
@@ -385,7 +398,7 @@ def test_loss_and_backward_match_fp64_reference(W, dim, K, reflected):
     lvl = [np.linalg.norm(grad[l * per:(l + 1) * per] - ref_grad[l * per:(l + 1) * per])
            / np.linalg.norm(ref_grad[l * per:(l + 1) * per]) for l in range(rcfg.L)]
     say("grid rel err per level: " + " ".join("%.1e" % e for e in lvl))
-    assert max(lvl) < 5e-3
+    assert max(lvl) < 1e-3
 
 
 def test_train_step_fits_known_target(W):
