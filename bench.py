@@ -1,18 +1,22 @@
 """Benchmark: guided vs uniform walk on stars on one MI355X.
 
-Workload (default): the 2D mixed problem -- a seeded star-shaped 4096-segment
-outer polygon with Neumann data of u = Re z^3, four circular Dirichlet holes,
-the 256x256 lattice restricted to the domain (43,347 query points), 256 walks
-per point.  One timed step is one guided solve of that workload with a fresh
-guide trained online (batches of walks with the frozen guide and training
-records, tail pass, Adam steps on the hash grid + MLP, repeated for the first
-quarter of the walks, then inference-only walks), i.e. every stage of the hot
-path.  ``value`` is its end-to-end walk steps per second.
+Default workload: the 3D Poisson problem at scale -- a seeded noise-displaced
+sphere of 1,003,520 triangles with three spherical holes, Neumann data on the
+upper half of the outer surface, Dirichlet data x^2 - y^2 elsewhere, a source
+of 16 seeded Gaussian bumps, 2^20 random interior query points.  One timed
+step is one training batch of the online guided solve: 4 walks per point
+(2^22 walks, guide frozen, every drawn direction recorded), the tail pass,
+the batch's training set drawn from its records and the Adam steps on the
+hash grid + MLP -- every stage of the hot path.  ``value`` is its walk steps
+per second, end to end.
 
-Also reported on the same line: the uniform-sampling solve of the same
-workload, relMSE / MSE of both against the closed form, MSE x time of both,
-the walk kernel's roofline position (algorithmic bytes from instrumented
-traversal counts), and the FP64 CPU oracle timed on a bounded sample.
+Also reported on the same line: guided vs uniform at equal time and at a
+fixed relative MSE (progressive runs of both over all 2^20 points; errors on
+4096 of them against a long uniform reference run), the walk kernel's
+roofline position, the guide MLP's MFMA rates, and the FP64 CPU oracle timed
+on a bounded sample of the same workload.  ``--workload c4`` / ``c3`` run the
+same line on the 215k-triangle slice problem or the 2D mixed problem, whose
+errors are taken against their closed forms.
 """
 from __future__ import annotations
 
@@ -29,6 +33,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak of one MI355X in lane operations: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (a wave64 instruction occupies a SIMD for 4 cycles); the
+# quoted 157.3 TFLOP/s fp32 vector peak counts a packed FMA as 4 operations
+VALU_PEAK_TLANE = 256 * 64 * 2.4e9 / 1e12
 # bytes read per four-wide node visit: child boxes and references, plus the
 # subtree measures (Neumann sample) or normal cones (silhouettes)
 NODE_BYTES = {d: {"closest_dirichlet": 16 * (2 * d + 1), "silhouette": 16 * (3 * d + 2),
@@ -53,7 +61,8 @@ def bytes_per_step(cost, dim):
 
 
 WALK_SOURCES = ["walk.hip", "walk_state.h", "geom_device.h", "guide_device.h", "walk_common.h", "wost_internal.h", "../build.py"]
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "walk_kernel2g_c3_guided_traffic.md")
+COUNTER_PROFILES = {"c5": "walk_kernel3g_c5_counters.md", "c4": "walk_kernel3g_c4_counters.md",
+                    "c3": "walk_kernel2g_c3_counters.md"}
 
 
 def walk_sources_sha256():
@@ -67,42 +76,49 @@ def walk_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the guided walk kernel from the committed
-    FETCH_SIZE / WRITE_SIZE summary, or None when that summary was taken on
-    other kernel sources than the ones built here."""
+def measured_traffic(workload):
+    """Per-launch counter figures of the guided walk kernel on a workload from
+    its committed rocprofv3 summary (a ``traffic-json:`` line): HBM bytes
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), VALU instructions and
+    the bound they establish; None when the summary was taken on other kernel
+    sources than the ones built here."""
+    path = os.path.join(ROOT, "profiles", COUNTER_PROFILES[workload])
     try:
-        with open(TRAFFIC_PROFILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 if line.startswith("traffic-json: "):
                     rec = json.loads(line[len("traffic-json: "):])
                     if rec.get("sources_sha256") == walk_sources_sha256():
+                        rec["path"] = path
                         return rec
     except OSError:
         pass
     return None
 
 
-def cpu_baseline(scene, max_seconds=20.0):
+def cpu_baseline(scene, max_seconds=15.0, n_pts=64, seed=3):
+    """The FP64 oracle (brute-force queries, uniform directions) on the host
+    cores, on a seeded sample of the workload's points with the walks per
+    point sized to about ``max_seconds`` of work."""
     import oracle
     oracle.build(force=False)
     o = oracle.OracleScene(scene)
-    idx = np.arange(0, scene.n_points, 32)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(scene.n_points, min(n_pts, scene.n_points), replace=False))
     pts = scene.points[idx]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # calibrate on a small slice, then size the sample to about max_seconds
+    # calibrate on one walk per point, then size the sample
     t0 = time.perf_counter()
-    r = o.solve(points=pts[:64], wpp=8, nthreads=cores)
+    r = o.solve(points=pts, wpp=1, nthreads=cores, point_ids=idx)
     dt = time.perf_counter() - t0
-    rate = r["steps"].sum() / max(dt, 1e-6)
-    wpp = int(np.clip(max_seconds * rate / (len(pts) * 14.0), 4, 256))
+    wpp = int(np.clip(max_seconds / max(dt, 1e-6), 1, 256))
     t0 = time.perf_counter()
-    r = o.solve(points=pts, wpp=wpp, nthreads=cores)
+    r = o.solve(points=pts, wpp=wpp, nthreads=cores, point_ids=idx, walk_offset=1)
     dt = time.perf_counter() - t0
     steps = int(r["steps"].sum())
     return {"value": steps / dt, "unit": "walk steps/s", "cores": cores, "kind": "oracle",
-            "sample": "%d query points (every 32nd lattice point) x %d walks = %d steps, FP64 brute-force, %.1f s"
-                      % (len(pts), wpp, steps, dt)}
+            "sample": "%d seeded query points x %d walks = %d steps of the same workload, FP64 brute-force queries, "
+                      "%.1f s" % (len(pts), wpp, steps, dt)}
 
 
 MFMA_F16_PEAK = 2.5e15   # dense FP16 MFMA FLOP/s of one MI355X
@@ -297,15 +313,230 @@ def run_lbvh(W, reps=5):
                           "lbvh_levels": bv.levels, "closest_queries_per_s": rates}), flush=True)
 
 
+# ------------------------------------------------------------------ workloads
+
+def setup_workload(W, name, wpp=None):
+    """Scene, geometry, query points and run settings of a workload."""
+    import torch
+
+    import scenes
+    if name == "c5":
+        s = scenes.scene_c5()
+        w = dict(desc="3D Poisson at scale: noise-displaced sphere, %d triangles (Neumann on the outer z > 0 half, "
+                      "x^2 - y^2 Dirichlet elsewhere, 3 Dirichlet holes), source of 16 Gaussian bumps, %d random "
+                      "interior points; guided: hash grid 16x2x2^19 + MLP 3x64, K=8 vMF, learned MIS, reflection; "
+                      "one step = one online training batch of 4 walks/point (2^22 walks, records, tail pass, "
+                      "Adam)" % (s.prims.shape[0], s.n_points),
+                 batch_wpp=4, train_until=8, guided_wpp=16, uniform_wpp=32, exact=None)
+    elif name == "c4":
+        s = scenes.scene_c4()
+        w = dict(desc="3D mixed Laplace: noise-displaced sphere, %d triangles (Neumann on the outer z > 0 half, "
+                      "x^2 - y^2), 3 Dirichlet holes, %d points of the 512^2 lattice on z = 0; guided: hash grid "
+                      "16x2x2^19 + MLP 3x64, K=8 vMF, learned MIS, reflection; one step = one online training batch "
+                      "of 16 walks/point" % (s.prims.shape[0], s.n_points),
+                 batch_wpp=16, train_until=64, guided_wpp=256, uniform_wpp=256,
+                 exact=lambda p: p[:, 0] ** 2 - p[:, 1] ** 2)
+    elif name == "c3":
+        s = scenes.scene_c2()
+        w = dict(desc="2D mixed Laplace: 4096-segment star polygon (Neumann, Re z^3), 4 Dirichlet holes, 256x256 "
+                      "lattice (%d points); guided: hash grid 8x2x2^16 + MLP 2x64, K=8 vMF, learned MIS, reflection; "
+                      "one step = one online training batch of 16 walks/point" % s.n_points,
+                 batch_wpp=16, train_until=64, guided_wpp=256, uniform_wpp=256,
+                 exact=lambda p: p[:, 0] ** 3 - 3 * p[:, 0] * p[:, 1] ** 2)
+    else:
+        raise ValueError(name)
+    if wpp:
+        w["guided_wpp"] = w["uniform_wpp"] = wpp
+    w.update(name=name, s=s, geom=W.Geometry.from_scene(s),
+             pts=torch.as_tensor(s.points, dtype=torch.float32, device="cuda"),
+             pb_u=W.Problem.from_scene(s), pb_g=W.Problem.from_scene(s, sampling="mis_learned"),
+             gcfg=W.GuideConfig.for_scene(s))
+    return w
+
+
+def _interp_loglog(ts, ys, y_star):
+    """Time at which a decreasing error curve (ts, ys) reaches y_star, by
+    interpolation of log t against log y between the bracketing points, or
+    extrapolation from the last two points (error ~ 1 / t) if never reached."""
+    lt, ly = np.log(np.asarray(ts, float)), np.log(np.asarray(ys, float))
+    ls = np.log(y_star)
+    for i in range(1, len(ts)):
+        if (ly[i - 1] - ls) * (ly[i] - ls) <= 0 and ly[i] != ly[i - 1]:
+            f = (ls - ly[i - 1]) / (ly[i] - ly[i - 1])
+            return float(np.exp(lt[i - 1] + f * (lt[i] - lt[i - 1])))
+    if ly[-1] > ls:         # not reached: follow error ~ 1/t from the last point
+        return float(np.exp(lt[-1] + (ly[-1] - ls)))
+    return float(np.exp(lt[0] - (ls - ly[0])))
+
+
+def _value_at(ts, ys, t_star):
+    """Error at time t_star by log-log interpolation (1/t extrapolation)."""
+    lt, ly = np.log(np.asarray(ts, float)), np.log(np.asarray(ys, float))
+    ls = np.log(t_star)
+    if ls <= lt[0]:
+        return float(np.exp(ly[0] - (ls - lt[0])))
+    if ls >= lt[-1]:
+        return float(np.exp(ly[-1] - (ls - lt[-1])))
+    return float(np.exp(np.interp(ls, lt, ly)))
+
+
+def compare_guided_uniform(W, wl, seed=900, n_ref=4096, ref_wpp=2048):
+    """Progressive guided (online training) and uniform solves over all the
+    workload's points, with the error logged after every batch on a seeded
+    subset of n_ref points: against the closed form where there is one, else
+    against a uniform reference run of ref_wpp walks on the subset (its own
+    variance subtracted).  Reports equal-time relMSE and the times at which
+    each method reaches r* = uniform's relMSE at its last checkpoint, with
+    MSE x time at r*."""
+    import torch
+
+    from paper_2410_18944_amd.driver import OnlineSchedule, OnlineSolver, Timer
+
+    s, pts = wl["s"], wl["pts"]
+    n = s.n_points
+    rng = np.random.default_rng(seed)
+    sub = np.sort(rng.choice(n, min(n_ref, n), replace=False))
+    sub_t = torch.as_tensor(sub, device="cuda")
+    ref_se2 = None
+    if wl["exact"] is not None:
+        ref = wl["exact"](s.points[sub])
+        ref_note = "closed form"
+    else:
+        acc_r = W.solve(wl["geom"], wl["pb_u"], pts[sub_t], ref_wpp, seed=seed + 7)
+        m, se, _ = acc_r.estimates()
+        ref, ref_se2 = m.cpu().numpy(), (se.cpu().numpy() ** 2)
+        ref_note = "uniform run of %d walks on the subset (its variance subtracted)" % ref_wpp
+
+    def errors(sum_, sq_, cnt_):
+        cnt = cnt_.double()
+        mean = (sum_ / cnt).cpu().numpy()
+        d2 = (mean - ref) ** 2
+        if ref_se2 is not None:
+            d2 = d2 - ref_se2
+        return float(np.mean(d2 / (ref ** 2 + 1e-2))), float(np.mean(d2))
+
+    def progressive(guided):
+        acc = W.Accumulator(n)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        evs, snaps, wpps = [], [], []
+        b = wl["batch_wpp"]
+        total = wl["guided_wpp"] if guided else wl["uniform_wpp"]
+        if guided:
+            g = W.Guide(wl["gcfg"], seed=seed + 1)
+            sch = OnlineSchedule(batch_wpp=b, train_until_wpp=wl["train_until"])
+            sol = OnlineSolver(wl["geom"], wl["pb_g"], pts, g, sch, seed=seed + 2, acc=acc, timer=Timer())
+        ev0.record()
+        done = 0
+        while done < total:
+            w = min(b, total - done)
+            if guided:
+                sol.batch(w, done, train=done < wl["train_until"])
+            else:
+                W.solve(wl["geom"], wl["pb_u"], pts, w, seed=seed + 3, walk_offset=done, acc=acc)
+            done += w
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            evs.append(e)
+            snaps.append((acc.sum[sub_t].clone(), acc.sum_sq[sub_t].clone(), acc.count[sub_t].clone()))
+            wpps.append(done)
+        torch.cuda.synchronize()
+        ts = [ev0.elapsed_time(e) * 1e-3 for e in evs]
+        errs = [errors(*sn) for sn in snaps]
+        st = acc.stats()
+        return dict(t=ts, rel_mse=[e[0] for e in errs], mse=[e[1] for e in errs], wpp=wpps,
+                    steps_per_walk=st["steps"] / max(st["walks"], 1), steps=st["steps"])
+
+    gu = progressive(True)
+    un = progressive(False)
+    r_star = un["rel_mse"][-1]
+    t_u = un["t"][-1]
+    t_g = _interp_loglog(gu["t"], gu["rel_mse"], r_star)
+    mse_star = un["mse"][-1]
+    t_eq = gu["t"][-1]
+    rel_u_eq = _value_at(un["t"], un["rel_mse"], t_eq)
+    out = {
+        "error_reference": ref_note, "error_points": int(len(sub)),
+        "equal_time": {"time_s": round(t_eq, 4), "rel_mse_guided": gu["rel_mse"][-1], "rel_mse_uniform": rel_u_eq,
+                       "uniform_over_guided": rel_u_eq / max(gu["rel_mse"][-1], 1e-300)},
+        "fixed_rel_mse": {"r_star": r_star, "defined_as": "uniform relMSE after %d walks/point" % wl["uniform_wpp"],
+                          "t_uniform_s": round(t_u, 4), "t_guided_s": round(t_g, 4),
+                          "mse_x_time_uniform": mse_star * t_u, "mse_x_time_guided": mse_star * t_g,
+                          "speedup_guided_over_uniform": t_u / t_g},
+        "guided": {"wpp": gu["wpp"], "t_s": [round(t, 4) for t in gu["t"]], "rel_mse": gu["rel_mse"],
+                   "steps_per_walk": gu["steps_per_walk"], "trained_through_wpp": wl["train_until"]},
+        "uniform": {"wpp": un["wpp"], "t_s": [round(t, 4) for t in un["t"]], "rel_mse": un["rel_mse"],
+                    "steps_per_walk": un["steps_per_walk"]},
+    }
+    return out
+
+
+def walk_roofline(W, wl, guide, total_steps, walk_s, n_launch):
+    """Roofline position of the guided walk kernel: algorithmic bytes per step
+    (nodes and primitives the six queries of a step read, counted by the
+    instrumented kernel on a sample of the workload) against the average
+    launch duration; the HBM bytes per launch measured by counters where the
+    committed counter summary matches the sources built here."""
+    import torch
+
+    from paper_2410_18944_amd import api
+
+    s, pts = wl["s"], wl["pts"]
+    d = s.dim
+    cost = torch.zeros(18, dtype=torch.int64, device="cuda")
+    api.set_cost_counters(cost)
+    sample = pts[:: max(1, s.n_points // 8192)]
+    a_g = W.solve(wl["geom"], wl["pb_g"], sample, 16, seed=5, guide=guide)
+    torch.cuda.synchronize()
+    api.set_cost_counters(None)
+    cost_g = api.cost_report(cost, a_g.stats()["steps"])
+    bps_g = bytes_per_step(cost_g, d)
+    avg_launch = walk_s / max(n_launch, 1)
+    alg_per_launch = total_steps * bps_g / max(n_launch, 1)
+    achieved = alg_per_launch / max(avg_launch, 1e-12) / 1e9
+    tr = measured_traffic(wl["name"])
+    kern = "wost::walk_kernel%dg<false> (guided %dD walk)" % (d, d)
+    out = {"kernel": kern, "bytes_per_step": round(bps_g, 1), "walk_s": round(walk_s, 4), "steps": total_steps,
+           "launches": n_launch, "avg_launch_ms": round(avg_launch * 1e3, 3),
+           "algorithmic_bytes_per_launch": round(alg_per_launch), "algorithmic_GBps": round(achieved, 2),
+           "algorithmic_hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+           "walk_sources_sha256": walk_sources_sha256()[:16],
+           "nodes_per_step": {q: round(c["nodes_per_step"], 2) for q, c in cost_g.items()},
+           "prims_per_step": {q: round(c["prims_per_step"], 2) for q, c in cost_g.items()},
+           # wave iterations over perfectly packed ones (64 x wave iterations / lane node visits)
+           "iterations_vs_packed": {q: round(c["divergence"], 2) for q, c in cost_g.items()}}
+    if tr:
+        # counter figures per launch (committed summary of the same kernel on
+        # the same workload) over this run's average launch duration
+        hbm = tr["hbm_bytes_per_launch"] / avg_launch / 1e9
+        valu = tr["valu_insts_per_launch"] * 64 / avg_launch / 1e12
+        out.update({"hbm_GBps_counters": round(hbm, 1), "hbm_frac_counters": round(hbm / HBM_PEAK_GBS, 4),
+                    "valu_Tlane_ops": round(valu, 3), "valu_frac": round(valu / VALU_PEAK_TLANE, 4),
+                    "counter_profile": os.path.relpath(tr["path"], ROOT), "counters": tr.get("counters")})
+        if tr["bound"] == "alu":
+            out.update({"bound": "alu", "achieved": round(valu, 3), "peak": VALU_PEAK_TLANE, "unit": "TFLOP/s",
+                        "frac": round(valu / VALU_PEAK_TLANE, 4), "traffic": round(tr["hbm_bytes_per_launch"]),
+                        "achieved_counts": "VALU lane operations (64 per wave instruction, counted by SQ_INSTS_VALU)"})
+        else:
+            out.update({"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": round(tr["hbm_bytes_per_launch"])})
+    else:
+        out.update({"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "note": "no counter summary for these kernel sources: algorithmic bytes against the HBM peak"})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--wpp", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["c5", "c4", "c3"], default="c5")
+    ap.add_argument("--wpp", type=int, default=0, help="walks per point of the comparison runs (0: workload default)")
     ap.add_argument("--batch-wpp", type=int, default=16)
     ap.add_argument("--train-until", type=int, default=64)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the guided-vs-uniform comparison")
     ap.add_argument("--print-walk-sha", action="store_true", help="print the walk kernel source hash and exit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
@@ -313,12 +544,17 @@ def main():
                     help="only time the standalone guide MLP (Adam step at 2^18, inference at 2^20) and exit")
     ap.add_argument("--engine-ab", action="store_true",
                     help="instead of the bench line: the persistent walk kernel against the multi-kernel "
-                         "wavefront solver on the bench workload")
+                         "wavefront solver on the 2D workload")
     ap.add_argument("--lbvh", action="store_true",
                     help="instead of the bench line: GPU linear-BVH build and query rate against the host build")
     ap.add_argument("--ablations", action="store_true",
                     help="instead of the bench line: sampling-mode ablations (K, selection c, reflection) and the "
-                         "training-schedule sweep on the same workload, one JSON line per configuration")
+                         "training-schedule sweep on the 2D workload, one JSON line per configuration")
+    ap.add_argument("--walk-only", action="store_true",
+                    help="only the timed online batches (for profiler runs): no roofline pass, guide MLP timing, "
+                         "comparison or CPU baseline")
+    ap.add_argument("--compare-only", action="store_true",
+                    help="only the guided-vs-uniform comparison of the workload, one JSON line")
     args = ap.parse_args()
     if args.print_walk_sha:
         print(walk_sources_sha256())
@@ -342,151 +578,107 @@ def main():
     import torch
 
     import paper_2410_18944_amd as W
-    from paper_2410_18944_amd import api
-    from paper_2410_18944_amd.driver import OnlineSchedule, online_solve
+    from paper_2410_18944_amd.driver import OnlineSchedule, OnlineSolver, Timer, online_solve
     import scenes
 
     torch.cuda.set_device(0)
-    s = scenes.scene_c2(wpp=args.wpp)
-    if args.guide_mlp:
-        print(json.dumps({"guide_mlp": guide_mlp_rates(W, W.GuideConfig.for_scene(s))}))
-        return
     if args.lbvh:
         run_lbvh(W)
         return
-    pts = torch.as_tensor(s.points, dtype=torch.float32, device="cuda")
-    u = s.points[:, 0] ** 3 - 3 * s.points[:, 0] * s.points[:, 1] ** 2
-    geom = W.Geometry.from_scene(s)
-    pb_u = W.Problem.from_scene(s)
-    pb_g = W.Problem.from_scene(s, sampling="mis_learned")
-    gcfg = W.GuideConfig.for_scene(s)
-    sched = OnlineSchedule(batch_wpp=args.batch_wpp, train_until_wpp=args.train_until)
+    if args.ablations or args.engine_ab:
+        s = scenes.scene_c2(wpp=256)
+        args.wpp = args.wpp or 256
+        pts = torch.as_tensor(s.points, dtype=torch.float32, device="cuda")
+        u = s.points[:, 0] ** 3 - 3 * s.points[:, 0] * s.points[:, 1] ** 2
+        geom = W.Geometry.from_scene(s)
+        if args.ablations:
+            run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args)
+        else:
+            run_engine_ab(W, online_solve, OnlineSchedule, s, geom, pts, u, args)
+        return
 
-    def guided_step(seed):
-        g = W.Guide(gcfg, seed=seed)
-        acc, info = online_solve(geom, pb_g, pts, args.wpp, g, sched, seed=18944 + seed)
-        return acc, info, g
+    t_setup = time.perf_counter()
+    wl = setup_workload(W, args.workload, args.wpp or None)
+    s = wl["s"]
+    if args.guide_mlp:
+        print(json.dumps({"guide_mlp": guide_mlp_rates(W, wl["gcfg"])}))
+        return
+    if args.compare_only:
+        print(json.dumps({"workload": args.workload, "comparison": compare_guided_uniform(W, wl)}))
+        return
+    setup_s = time.perf_counter() - t_setup
 
-    def uniform_step(seed):
-        acc = W.solve(geom, pb_u, pts, args.wpp, seed=18944 + seed)
-        return acc
-
-    for w in range(args.warmup):
-        guided_step(100 + w)
-        uniform_step(100 + w)
+    # ---- the online solve whose training batches are the timed steps
+    b = wl["batch_wpp"]
+    g = W.Guide(wl["gcfg"], seed=1)
+    sch = OnlineSchedule(batch_wpp=b, train_until_wpp=b * (args.warmup + args.steps))
+    timer = Timer()
+    sol = OnlineSolver(wl["geom"], wl["pb_g"], wl["pts"], g, sch, seed=18944, timer=timer)
+    for k in range(args.warmup):
+        sol.batch(b, k * b, train=True)
     torch.cuda.synchronize()
-    if args.ablations:
-        run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args)
-        return
-    if args.engine_ab:
-        run_engine_ab(W, online_solve, OnlineSchedule, s, geom, pts, u, args)
-        return
-
-    # ---- timed region: K guided solves
+    st0 = sol.acc.stats()
+    n_ev0 = len(timer.events.get("walk0", []))
     t0 = time.perf_counter()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    total_steps = 0
-    walk_s = train_s = tail_s = 0.0
-    n_launch = 0
-    last = None
-    for k in range(args.steps):
-        acc, info, g = guided_step(k + 1)
-        st = acc.stats()
-        total_steps += st["steps"]
-        walk_s += info["phase_s"]["walk"]
-        n_launch += info["walk_launches"]
-        train_s += info["phase_s"]["train"]
-        tail_s += info["phase_s"]["tail"]
-        last = (acc, info, g)
+    for k in range(args.warmup, args.warmup + args.steps):
+        sol.batch(b, k * b, train=True)
     e1.record()
     torch.cuda.synchronize()
     elapsed = e0.elapsed_time(e1) * 1e-3
     wall = time.perf_counter() - t0
-    ms_per_step = elapsed / args.steps * 1e3
+    st1 = sol.acc.stats()
+    total_steps = st1["steps"] - st0["steps"]
     value = total_steps / elapsed
+    # phase split of the timed batches (events on the launch stream)
+    ph = {k: 0.0 for k in ("walk", "tail", "train")}
+    pairs = {"walk": ("walk0", "walk1"), "tail": ("walk1", "tail1"), "train": ("train0", "train1")}
+    for name, (a, bb) in pairs.items():
+        ea, eb = timer.events.get(a, [])[n_ev0:], timer.events.get(bb, [])[n_ev0:]
+        ph[name] = sum(x.elapsed_time(y) for x, y in zip(ea, eb)) * 1e-3
+    info = sol.finish()
+    if args.walk_only:
+        print(json.dumps({"workload": args.workload, "value": round(value, 1), "unit": "walk steps/s",
+                          "steps": args.steps, "walk_phase_s": ph["walk"], "avg_launch_ms": ph["walk"] / args.steps * 1e3,
+                          "walk_steps": total_steps}))
+        return
 
-    acc_g, info_g, g_last = last
-    m_g = acc_g.estimates()[0].cpu().numpy()
-    st_g = acc_g.stats()
-    # ---- uniform solve of the same workload (not part of `value`)
-    u_e0 = torch.cuda.Event(enable_timing=True)
-    u_e1 = torch.cuda.Event(enable_timing=True)
-    u_e0.record()
-    acc_u = uniform_step(1)
-    u_e1.record()
-    torch.cuda.synchronize()
-    t_u = u_e0.elapsed_time(u_e1) * 1e-3
-    m_u = acc_u.estimates()[0].cpu().numpy()
-    st_u = acc_u.stats()
-    t_g = elapsed / args.steps
-    mse_g = float(np.mean((m_g - u) ** 2))
-    mse_u = float(np.mean((m_u - u) ** 2))
-
-    # ---- roofline of the walk kernel: algorithmic bytes per step from an
-    # instrumented pass over a sample of the same workload
-    cost = torch.zeros(18, dtype=torch.int64, device="cuda")
-    api.set_cost_counters(cost)
-    sample = pts[:: max(1, s.n_points // 8192)]
-    a_u = W.solve(geom, pb_u, sample, 16, seed=5)
-    torch.cuda.synchronize()
-    bps_u = bytes_per_step(api.cost_report(cost, a_u.stats()["steps"]), 2)
-    cost.zero_()
-    a_g = W.solve(geom, pb_g, sample, 16, seed=5, guide=g_last)
-    torch.cuda.synchronize()
-    api.set_cost_counters(None)
-    cost_g = api.cost_report(cost, a_g.stats()["steps"])
-    bps_g = bytes_per_step(cost_g, 2)
-    # dominant kernel: the guided walk kernel; time = walk phase of the timed solves
-    achieved = total_steps * bps_g / max(walk_s, 1e-9) / 1e9
-    tr = measured_traffic()
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": round(tr["hbm_bytes_per_launch"]) if tr else None,
-                "kernel": "wost::walk_kernel2g<false> (guided 2D walk)",
-                "bytes_per_step": round(bps_g, 1), "uniform_bytes_per_step": round(bps_u, 1),
-                "walk_s": round(walk_s, 4), "steps": total_steps,
-                "launches": n_launch, "avg_launch_ms": round(walk_s / max(n_launch, 1) * 1e3, 3),
-                "algorithmic_bytes_per_launch": round(total_steps * bps_g / max(n_launch, 1)),
-                "walk_sources_sha256": walk_sources_sha256()[:16]}
-
-    mlp = guide_mlp_rates(W, gcfg)
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(s)
+    roof = walk_roofline(W, wl, g, total_steps, ph["walk"], args.steps)
+    mlp = guide_mlp_rates(W, wl["gcfg"])
+    comp = None if args.no_compare else compare_guided_uniform(W, wl)
+    cpu = None if args.no_cpu else cpu_baseline(s)
 
     out = {
-        "metric": "walk steps/s (guided WoSt, online training, end-to-end) + MSE x time guided vs uniform",
+        "metric": "walk steps/s (guided WoSt, online training, end-to-end) + MSE x time guided vs uniform at fixed "
+                  "relative MSE",
         "value": round(value, 1),
         "unit": "walk steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D mixed Laplace: 4096-segment star polygon (Neumann, Re z^3), 4 Dirichlet holes, "
-                               "256x256 lattice (%d points), %d walks/point, guided (hash grid 8x2x2^16 + MLP 2x64, "
-                               "K=8 vMF, learned MIS, reflection), online training in %d-wpp batches for the first %d wpp"
-                               % (s.n_points, args.wpp, args.batch_wpp, args.train_until),
-                   "points": s.n_points, "wpp": args.wpp, "seed": 2410},
-        "roofline": roofline,
+        "config": {"workload": wl["desc"], "points": s.n_points, "walks_per_step": s.n_points * b, "seed": 2410},
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
         "cpu_baseline": cpu,
+        "walk_kernel": {k: v for k, v in roof.items() if k not in ("bound", "achieved", "peak", "unit", "frac",
+                                                                     "traffic")},
+        "guided_step": {"walk_phase_s": round(ph["walk"] / args.steps, 4),
+                        "tail_phase_s": round(ph["tail"] / args.steps, 4),
+                        "train_phase_s": round(ph["train"] / args.steps, 4),
+                        "adam_steps": info["adam_steps"], "records": info["records"],
+                        "records_dropped": info["records_dropped"],
+                        "steps_per_walk": (st1["steps"] - st0["steps"]) / max(st1["walks"] - st0["walks"], 1),
+                        "walk_steps_per_s_walk_phase": round(total_steps / max(ph["walk"], 1e-9), 1)},
+        "comparison": comp,
         "guide_mlp": mlp,
-        "guided": {"steps_per_s_end_to_end": round(value, 1), "walk_phase_s": round(walk_s / args.steps, 4),
-                   "train_phase_s": round(train_s / args.steps, 4), "tail_phase_s": round(tail_s / args.steps, 4),
-                   "time_s": round(t_g, 4), "rel_mse": rel_mse(m_g, u), "mse": mse_g, "mse_x_time": mse_g * t_g,
-                   "adam_steps": info_g["adam_steps"], "records": info_g["records"],
-                   "steps_per_walk": st_g["steps"] / max(st_g["walks"], 1)},
-        "uniform": {"steps_per_s": round(st_u["steps"] / t_u, 1), "time_s": round(t_u, 4),
-                    "rel_mse": rel_mse(m_u, u), "mse": mse_u, "mse_x_time": mse_u * t_u,
-                    "steps_per_walk": st_u["steps"] / max(st_u["walks"], 1)},
-        "mse_x_time_speedup_guided_over_uniform": (mse_u * t_u) / max(mse_g * t_g, 1e-300),
+        "setup_s": round(setup_s, 2),
         "wall_s": round(wall, 3),
     }
     print(json.dumps(out))

@@ -355,6 +355,15 @@ typedef struct {
  * the per-walk output of the wost_solve call that wrote the records. */
 int wost_tail_pass(int32_t dim, const wost_records* rec, const float* walk_value, int64_t n_slots,
                    void* stream);
+/* The training set of a batch (Sec. 5.2 "Online Training Scheme": the
+ * guide is trained on the samples of the batch just taken): m rows drawn
+ * uniformly with replacement from the rows `src` holds (its device count,
+ * at most its capacity), by Philox4x32-10 under `seed`, copied into rows
+ * 0..m-1 of `dst`; dst's count is set to m (0 if src is empty).  Minibatches
+ * taken as contiguous ranges of dst then mix records of all the batch's
+ * walks.  WOST_ESIZE if m exceeds dst's capacity. */
+int wost_records_sample(int32_t dim, const wost_records* src, uint64_t seed, int64_t m, const wost_records* dst,
+                        void* stream);
 /* Workspace bytes for wost_guide_loss_bwd / wost_guide_train_step on `count`
  * records (per-workgroup partial weight gradients). */
 int64_t wost_guide_train_workspace_bytes(const wost_guide* g, int64_t count);
@@ -444,10 +453,11 @@ int wost_geom_use_dirichlet_lbvh(wost_geom* g, const float* nodes, int32_t n_nod
  * results. */
 int wost_set_launch(int32_t waves_per_cu);
 /* Walk pool of the persistent kernel.  Each wave keeps `slots_per_wave`
- * walks in flight (a multiple of 64 in [64, 8192]; 0 = default 384) and
- * advances all of them one star per round, query by query; a lane whose
- * query has finished takes the next walk of that query's list, once at least
- * `refill_batch` lanes (1..64; 0 = default 32) are waiting or no lane is
+ * walks in flight (a multiple of 64 in [64, 8192]; 0 = the default of the
+ * solve's dimension: 384 in 2D, 1536 in 3D) and advances all of them one
+ * star per round, query by query; a lane whose query has finished takes the
+ * next walk of that query's list, once at least `refill_batch` lanes (1..64;
+ * 0 = default: 32 in 2D, 8 in 3D) are waiting or no lane is
  * still traversing.  Larger pools keep more lanes busy at the cost of
  * workspace.  Process wide; affects throughput and workspace size only,
  * never results.  Call wost_solve_workspace_bytes after changing it. */

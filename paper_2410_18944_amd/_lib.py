@@ -96,6 +96,7 @@ SIGNATURES = {
     "wost_guide_loss_fwd": (_I, [_P, C.POINTER(wost_records), _I64, _I64, _F, _P, _P]),
     "wost_guide_loss_bwd": (_I, [_P, C.POINTER(wost_records), _I64, _I64, _F, _F, _P, _P, _P, _I64, _P]),
     "wost_guide_adam_step": (_I, [_P, C.POINTER(wost_adam), _P]),
+    "wost_records_sample": (_I, [_I32, C.POINTER(wost_records), _U64, _I64, C.POINTER(wost_records), _P]),
     "wost_guide_train_step": (_I, [_P, C.POINTER(wost_records), _I64, _I64, C.POINTER(wost_adam), _P, _P, _I64, _P]),
     "wost_guide_train_step_noalloc": (_I, [_P, C.POINTER(wost_records), _I64, _I64, C.POINTER(wost_adam), _P, _P]),
     "wost_guide_train_workspace_bytes": (_I64, [_P, _I64]),

@@ -653,6 +653,30 @@ __global__ void tail_pass_kernel(float* rec, int64_t cap, const unsigned long lo
     rec[(int64_t)(3 * dim + 4) * cap + i] = pt;
 }
 
+// Training set of a batch: row i of dst is a copy of a row of src drawn
+// uniformly (with replacement) by Philox4x32-10 word (i, 0, 0, 0) under the
+// key (seed lo, seed hi), so minibatches mix records of every walk of the
+// batch instead of the runs of records one wave appended together.
+__global__ void records_sample_kernel(const float* __restrict__ src, int64_t src_cap,
+                                      const unsigned long long* __restrict__ src_count, int nf, float* __restrict__ dst,
+                                      int64_t dst_cap, int64_t m, uint32_t k0, uint32_t k1)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int64_t n = (int64_t)min((unsigned long long)src_cap, *src_count);
+    if (n <= 0) return;
+    const uint4 w = philox(make_uint4((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u), k0, k1);
+    // index floor(u n) for the 64-bit fraction u of two words
+    const uint64_t u64 = ((uint64_t)w.x << 32) | (uint64_t)w.y;
+    const int64_t j = (int64_t)__umul64hi(u64, (uint64_t)n);
+    for (int f = 0; f < nf; ++f) dst[(int64_t)f * dst_cap + i] = src[(int64_t)f * src_cap + j];
+}
+
+__global__ void set_count_kernel(unsigned long long* dst, const unsigned long long* src, unsigned long long m)
+{
+    if (threadIdx.x == 0) *dst = *src > 0 ? m : 0ull;
+}
+
 static int g_train_cu = 0;
 
 static int train_grid_cap()
@@ -841,6 +865,32 @@ extern "C" int wost_tail_pass(int32_t dim, const wost_records* rec, const float*
                        rec->capacity, (const unsigned long long*)rec->count, dim, walk_value, n_slots);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("wost_tail_pass: %s", hipGetErrorString(e)); return WOST_EHIP; }
+    return WOST_OK;
+}
+
+extern "C" int wost_records_sample(int32_t dim, const wost_records* src, uint64_t seed, int64_t m,
+                                   const wost_records* dst, void* stream)
+{
+    if ((dim != 2 && dim != 3) || !src || !src->data || !src->count || !dst || !dst->data || !dst->count || m < 0) {
+        set_error("wost_records_sample: bad arguments");
+        return WOST_EINVAL;
+    }
+    if (m > dst->capacity) {
+        set_error("wost_records_sample: %lld rows do not fit the destination (%lld)", (long long)m,
+                  (long long)dst->capacity);
+        return WOST_ESIZE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (m > 0 && src->capacity > 0)
+        hipLaunchKernelGGL(records_sample_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, src->data,
+                           src->capacity, (const unsigned long long*)src->count, 3 * dim + 5, dst->data, dst->capacity,
+                           m, (uint32_t)seed, (uint32_t)(seed >> 32));
+    // the destination holds m rows (zero if the source is empty: the rows
+    // are then left unwritten and must not be trained on)
+    hipLaunchKernelGGL(set_count_kernel, dim3(1), dim3(64), 0, s, (unsigned long long*)dst->count,
+                       (const unsigned long long*)src->count, (unsigned long long)m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) { set_error("wost_records_sample: %s", hipGetErrorString(e)); return WOST_EHIP; }
     return WOST_OK;
 }
 

@@ -186,3 +186,10 @@ class GuideLoss(torch.autograd.Function):
         grad = torch.zeros_like(g.master)
         g.loss_bwd(ctx.records, ctx.begin, ctx.count, ctx.e_mis, scale=1.0, dloss=dloss.float(), grad=grad)
         return grad, None, None, None, None, None
+
+
+def sample_records(src, seed, m, dst):
+    """dst <- m rows of src drawn uniformly with replacement (wost_records_sample)."""
+    a, b = src.to_c(), dst.to_c()
+    L.check(L.load().wost_records_sample(src.dim, C.byref(a), int(seed), int(m), C.byref(b), _stream()),
+            "wost_records_sample")

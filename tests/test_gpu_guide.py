@@ -453,3 +453,38 @@ def test_train_step_fits_known_target(W):
     dens = np.array([G.mixture_pdf(mu_t[None], mu[i], kappa[i], lam[i])[0] for i in range(n_pos)])
     say("density at target mean / target peak", np.round(dens / peak, 3))
     assert np.all(dens > 0.5 * peak), dens / peak
+
+
+def test_records_sample_draws_rows_uniformly(W):
+    """wost_records_sample: every drawn row is a whole row of the source
+    (all fields of one record), rows are drawn uniformly over the source's
+    written rows, the destination count is m, and an empty source yields an
+    empty training set."""
+    from paper_2410_18944_amd.guide import sample_records
+    from scipy import stats
+    n_src, cap, m = 5000, 6000, 1 << 20
+    src = W.Records(3, capacity=cap)
+    D = np.zeros((14, cap), np.float32)
+    D[:, :n_src] = np.arange(n_src, dtype=np.float32)[None, :] + np.arange(14, dtype=np.float32)[:, None] * 1e5
+    src.data.copy_(torch.as_tensor(D))
+    src.count.fill_(n_src)
+    dst = W.Records(3, capacity=m)
+    sample_records(src, 77, m, dst)
+    torch.cuda.synchronize()
+    assert int(dst.count.item()) == m
+    out = dst.data.cpu().numpy()
+    row = out[0].astype(np.int64)
+    assert row.min() >= 0 and row.max() < n_src
+    np.testing.assert_array_equal(out, row[None, :].astype(np.float32) + np.arange(14, dtype=np.float32)[:, None] * 1e5)
+    cnt = np.bincount(row, minlength=n_src)
+    chi2 = np.sum((cnt - m / n_src) ** 2 / (m / n_src))
+    assert stats.chi2.sf(chi2, n_src - 1) > 1e-6, chi2
+    # another seed draws another sample; an empty source gives count 0
+    dst2 = W.Records(3, capacity=m)
+    sample_records(src, 78, m, dst2)
+    src.count.zero_()
+    dst3 = W.Records(3, capacity=16)
+    sample_records(src, 79, 16, dst3)
+    torch.cuda.synchronize()
+    assert not torch.equal(dst.data, dst2.data)
+    assert int(dst3.count.item()) == 0
