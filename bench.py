@@ -45,6 +45,14 @@ NODE_BYTES = {d: {"closest_dirichlet": 16 * (2 * d + 1), "silhouette": 16 * (3 *
 PRIM_BYTES = {2: {"dir": 16, "sil": 32, "neu": 32}, 3: {"dir": 48, "sil": 64, "neu": 64}}
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries the one JSON line)."""
+    print("[bench %.0fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
 def rel_mse(est, exact, delta=1e-2):
     return float(np.mean((est - exact) ** 2 / (exact ** 2 + delta)))
 
@@ -66,13 +74,21 @@ COUNTER_PROFILES = {"c5": "walk_kernel3g_c5_counters.md", "c4": "walk_kernel3g_c
 
 
 def walk_sources_sha256():
-    """Hash of the sources and build flags of the walk kernel."""
+    """Hash of the sources and build flags of the walk kernel, comments and
+    blank space left out (a comment edit does not change the kernel)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2410_18944_amd", "csrc")
     for f in WALK_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        if f.endswith(".py"):
+            text = re.sub(r"#[^\n]*", "", text)
+        else:
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+        h.update(re.sub(r"\s+", " ", text).strip().encode())
     return h.hexdigest()
 
 
@@ -315,8 +331,9 @@ def run_lbvh(W, reps=5):
 
 # ------------------------------------------------------------------ workloads
 
-def setup_workload(W, name, wpp=None):
-    """Scene, geometry, query points and run settings of a workload."""
+def setup_workload(W, name, wpp=None, points=0, batch_wpp=0, train_until=0, uniform_wpp=0):
+    """Scene, geometry, query points and run settings of a workload; the
+    keyword arguments override the defaults (points: a seeded subset)."""
     import torch
 
     import scenes
@@ -326,27 +343,37 @@ def setup_workload(W, name, wpp=None):
                       "x^2 - y^2 Dirichlet elsewhere, 3 Dirichlet holes), source of 16 Gaussian bumps, %d random "
                       "interior points; guided: hash grid 16x2x2^19 + MLP 3x64, K=8 vMF, learned MIS, reflection; "
                       "one step = one online training batch of 4 walks/point (2^22 walks, records, tail pass, "
-                      "Adam)" % (s.prims.shape[0], s.n_points),
-                 batch_wpp=4, train_until=8, guided_wpp=16, uniform_wpp=32, exact=None)
+                      "48 Adam steps on 2^18 records)" % (s.prims.shape[0], s.n_points),
+                 batch_wpp=4, train_until=16, guided_wpp=64, uniform_wpp=64, adam_steps=48, exact=None)
     elif name == "c4":
         s = scenes.scene_c4()
         w = dict(desc="3D mixed Laplace: noise-displaced sphere, %d triangles (Neumann on the outer z > 0 half, "
                       "x^2 - y^2), 3 Dirichlet holes, %d points of the 512^2 lattice on z = 0; guided: hash grid "
                       "16x2x2^19 + MLP 3x64, K=8 vMF, learned MIS, reflection; one step = one online training batch "
                       "of 16 walks/point" % (s.prims.shape[0], s.n_points),
-                 batch_wpp=16, train_until=64, guided_wpp=256, uniform_wpp=256,
+                 batch_wpp=64, train_until=256, guided_wpp=1024, uniform_wpp=1024, adam_steps=48, compare_points=16384,
                  exact=lambda p: p[:, 0] ** 2 - p[:, 1] ** 2)
     elif name == "c3":
         s = scenes.scene_c2()
         w = dict(desc="2D mixed Laplace: 4096-segment star polygon (Neumann, Re z^3), 4 Dirichlet holes, 256x256 "
                       "lattice (%d points); guided: hash grid 8x2x2^16 + MLP 2x64, K=8 vMF, learned MIS, reflection; "
                       "one step = one online training batch of 16 walks/point" % s.n_points,
-                 batch_wpp=16, train_until=64, guided_wpp=256, uniform_wpp=256,
+                 batch_wpp=16, train_until=64, guided_wpp=256, uniform_wpp=256, adam_steps=16,
                  exact=lambda p: p[:, 0] ** 3 - 3 * p[:, 0] * p[:, 1] ** 2)
     else:
         raise ValueError(name)
     if wpp:
         w["guided_wpp"] = w["uniform_wpp"] = wpp
+    if uniform_wpp:
+        w["uniform_wpp"] = uniform_wpp
+    if batch_wpp:
+        w["batch_wpp"] = batch_wpp
+    if train_until:
+        w["train_until"] = train_until
+    if points and points < s.n_points:
+        idx = np.sort(np.random.default_rng(1234).choice(s.n_points, points, replace=False))
+        s = s.subset(idx)
+        w["desc"] += "; a seeded subset of %d points" % points
     w.update(name=name, s=s, geom=W.Geometry.from_scene(s),
              pts=torch.as_tensor(s.points, dtype=torch.float32, device="cuda"),
              pb_u=W.Problem.from_scene(s), pb_g=W.Problem.from_scene(s, sampling="mis_learned"),
@@ -393,6 +420,12 @@ def compare_guided_uniform(W, wl, seed=900, n_ref=4096, ref_wpp=2048):
     from paper_2410_18944_amd.driver import OnlineSchedule, OnlineSolver, Timer
 
     s, pts = wl["s"], wl["pts"]
+    cp = wl.get("compare_points", 0)
+    if cp and cp < s.n_points:
+        # the comparison runs on a seeded subset of the points (the timed
+        # steps use all of them)
+        idx = np.sort(np.random.default_rng(seed + 5).choice(s.n_points, cp, replace=False))
+        s, pts = s.subset(idx), pts[torch.as_tensor(idx, device=pts.device)]
     n = s.n_points
     rng = np.random.default_rng(seed)
     sub = np.sort(rng.choice(n, min(n_ref, n), replace=False))
@@ -423,7 +456,8 @@ def compare_guided_uniform(W, wl, seed=900, n_ref=4096, ref_wpp=2048):
         total = wl["guided_wpp"] if guided else wl["uniform_wpp"]
         if guided:
             g = W.Guide(wl["gcfg"], seed=seed + 1)
-            sch = OnlineSchedule(batch_wpp=b, train_until_wpp=wl["train_until"])
+            sch = OnlineSchedule(batch_wpp=b, train_until_wpp=wl["train_until"],
+                                 max_steps_per_batch=wl["adam_steps"])
             sol = OnlineSolver(wl["geom"], wl["pb_g"], pts, g, sch, seed=seed + 2, acc=acc, timer=Timer())
         ev0.record()
         done = 0
@@ -437,6 +471,9 @@ def compare_guided_uniform(W, wl, seed=900, n_ref=4096, ref_wpp=2048):
             e = torch.cuda.Event(enable_timing=True)
             e.record()
             evs.append(e)
+            if done % (8 * b) == 0 or done == total:
+                torch.cuda.synchronize()
+                progress("comparison, %s: %d of %d walks per point" % ("guided" if guided else "uniform", done, total))
             snaps.append((acc.sum[sub_t].clone(), acc.sum_sq[sub_t].clone(), acc.count[sub_t].clone()))
             wpps.append(done)
         torch.cuda.synchronize()
@@ -455,6 +492,7 @@ def compare_guided_uniform(W, wl, seed=900, n_ref=4096, ref_wpp=2048):
     t_eq = gu["t"][-1]
     rel_u_eq = _value_at(un["t"], un["rel_mse"], t_eq)
     out = {
+        "points": int(n), "batch_wpp": wl["batch_wpp"], "adam_steps_per_batch": wl["adam_steps"],
         "error_reference": ref_note, "error_points": int(len(sub)),
         "equal_time": {"time_s": round(t_eq, 4), "rel_mse_guided": gu["rel_mse"][-1], "rel_mse_uniform": rel_u_eq,
                        "uniform_over_guided": rel_u_eq / max(gu["rel_mse"][-1], 1e-300)},
@@ -507,18 +545,22 @@ def walk_roofline(W, wl, guide, total_steps, walk_s, n_launch):
     if tr:
         # counter figures per launch (committed summary of the same kernel on
         # the same workload) over this run's average launch duration
-        hbm = tr["hbm_bytes_per_launch"] / avg_launch / 1e9
-        valu = tr["valu_insts_per_launch"] * 64 / avg_launch / 1e12
+        # per walk step (the profiled batch) x this run's steps per launch
+        steps_per_launch = total_steps / max(n_launch, 1)
+        hbm = tr["hbm_bytes_per_step"] * steps_per_launch / avg_launch / 1e9
+        valu = tr["valu_insts_per_step"] * steps_per_launch * 64 / avg_launch / 1e12
         out.update({"hbm_GBps_counters": round(hbm, 1), "hbm_frac_counters": round(hbm / HBM_PEAK_GBS, 4),
                     "valu_Tlane_ops": round(valu, 3), "valu_frac": round(valu / VALU_PEAK_TLANE, 4),
                     "counter_profile": os.path.relpath(tr["path"], ROOT), "counters": tr.get("counters")})
         if tr["bound"] == "alu":
             out.update({"bound": "alu", "achieved": round(valu, 3), "peak": VALU_PEAK_TLANE, "unit": "TFLOP/s",
-                        "frac": round(valu / VALU_PEAK_TLANE, 4), "traffic": round(tr["hbm_bytes_per_launch"]),
+                        "frac": round(valu / VALU_PEAK_TLANE, 4),
+                        "traffic": round(tr["hbm_bytes_per_step"] * steps_per_launch),
                         "achieved_counts": "VALU lane operations (64 per wave instruction, counted by SQ_INSTS_VALU)"})
         else:
             out.update({"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": round(tr["hbm_bytes_per_launch"])})
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": round(tr["hbm_bytes_per_step"] * steps_per_launch)})
     else:
         out.update({"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
@@ -533,8 +575,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=["c5", "c4", "c3"], default="c5")
     ap.add_argument("--wpp", type=int, default=0, help="walks per point of the comparison runs (0: workload default)")
-    ap.add_argument("--batch-wpp", type=int, default=16)
-    ap.add_argument("--train-until", type=int, default=64)
+    ap.add_argument("--batch-wpp", type=int, default=0, help="walks per point per batch (0: workload default)")
+    ap.add_argument("--train-until", type=int, default=0, help="train through this many walks per point (0: default)")
+    ap.add_argument("--uniform-wpp", type=int, default=0, help="walks per point of the uniform comparison run")
+    ap.add_argument("--points", type=int, default=0, help="use a seeded subset of this many points (0: all)")
+    ap.add_argument("--adam-steps", type=int, default=0, help="Adam steps per training batch (0: workload default)")
+    ap.add_argument("--ref-points", type=int, default=4096, help="points on which the comparison measures errors")
+    ap.add_argument("--ref-wpp", type=int, default=2048, help="walks per point of the reference run (no closed form)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the guided-vs-uniform comparison")
     ap.add_argument("--print-walk-sha", action="store_true", help="print the walk kernel source hash and exit")
@@ -588,6 +635,8 @@ def main():
     if args.ablations or args.engine_ab:
         s = scenes.scene_c2(wpp=256)
         args.wpp = args.wpp or 256
+        args.batch_wpp = args.batch_wpp or 16
+        args.train_until = args.train_until or 64
         pts = torch.as_tensor(s.points, dtype=torch.float32, device="cuda")
         u = s.points[:, 0] ** 3 - 3 * s.points[:, 0] * s.points[:, 1] ** 2
         geom = W.Geometry.from_scene(s)
@@ -598,25 +647,32 @@ def main():
         return
 
     t_setup = time.perf_counter()
-    wl = setup_workload(W, args.workload, args.wpp or None)
+    wl = setup_workload(W, args.workload, args.wpp or None, points=args.points, batch_wpp=args.batch_wpp,
+                        train_until=args.train_until, uniform_wpp=args.uniform_wpp)
+    if args.adam_steps:
+        wl["adam_steps"] = args.adam_steps
     s = wl["s"]
     if args.guide_mlp:
         print(json.dumps({"guide_mlp": guide_mlp_rates(W, wl["gcfg"])}))
         return
     if args.compare_only:
-        print(json.dumps({"workload": args.workload, "comparison": compare_guided_uniform(W, wl)}))
+        print(json.dumps({"workload": args.workload, "points": s.n_points, "batch_wpp": wl["batch_wpp"],
+                          "train_until": wl["train_until"], "adam_steps": wl["adam_steps"],
+                          "comparison": compare_guided_uniform(W, wl, n_ref=args.ref_points, ref_wpp=args.ref_wpp)}))
         return
     setup_s = time.perf_counter() - t_setup
 
     # ---- the online solve whose training batches are the timed steps
     b = wl["batch_wpp"]
     g = W.Guide(wl["gcfg"], seed=1)
-    sch = OnlineSchedule(batch_wpp=b, train_until_wpp=b * (args.warmup + args.steps))
+    sch = OnlineSchedule(batch_wpp=b, train_until_wpp=b * (args.warmup + args.steps),
+                         max_steps_per_batch=wl["adam_steps"])
     timer = Timer()
     sol = OnlineSolver(wl["geom"], wl["pb_g"], wl["pts"], g, sch, seed=18944, timer=timer)
     for k in range(args.warmup):
         sol.batch(b, k * b, train=True)
     torch.cuda.synchronize()
+    progress("%s: set-up and %d warm-up batches done" % (args.workload, args.warmup))
     st0 = sol.acc.stats()
     n_ev0 = len(timer.events.get("walk0", []))
     t0 = time.perf_counter()
@@ -625,6 +681,10 @@ def main():
     e0.record()
     for k in range(args.warmup, args.warmup + args.steps):
         sol.batch(b, k * b, train=True)
+        if (k - args.warmup) % 5 == 4:
+            # the host already waits on every batch's record count, so this
+            # progress line costs the timed region nothing
+            progress("timed batch %d of %d" % (k - args.warmup + 1, args.steps))
     e1.record()
     torch.cuda.synchronize()
     elapsed = e0.elapsed_time(e1) * 1e-3
@@ -645,9 +705,13 @@ def main():
                           "walk_steps": total_steps}))
         return
 
+    progress("timed region done: %.3e walk steps/s" % value)
     roof = walk_roofline(W, wl, g, total_steps, ph["walk"], args.steps)
     mlp = guide_mlp_rates(W, wl["gcfg"])
-    comp = None if args.no_compare else compare_guided_uniform(W, wl)
+    progress("roofline pass and guide MLP rates done")
+    comp = None if args.no_compare else compare_guided_uniform(W, wl, n_ref=args.ref_points, ref_wpp=args.ref_wpp)
+    if not args.no_cpu:
+        progress("CPU oracle baseline")
     cpu = None if args.no_cpu else cpu_baseline(s)
 
     out = {

@@ -1,13 +1,18 @@
 // Persistent walk-on-stars kernel for gfx950, the per-point FP64 reduction,
-// batched geometric queries, and their C ABI (wost_solve, wost_query).
+// batched geometric queries, and their C ABI (wost_solve, wost_query,
+// wost_neumann_sample).
 //
-// One lane carries one walk.  Each workgroup is a single 64-wide wavefront
-// that loops until the global walk counter is exhausted: at the top of every
-// step the lanes whose walk finished are refilled together (one atomic per
-// wave, lane offsets from mbcnt over the ballot of free lanes), so the wave
-// stays full while work remains.  A step visits one star (Sec. 3.2): closest
-// Dirichlet point and epsilon-shell test, closest Neumann silhouette -> radius,
-// Neumann and source contributions, direction draw, first hit in the star.
+// Each workgroup is a single 64-wide wavefront that owns a pool of walk
+// slots (structure of arrays in the caller's workspace) and loops until the
+// global walk counter is exhausted.  A round advances every live walk of the
+// pool by one star (Sec. 3.2), one query at a time: step update and refill
+// of empty slots (chunks of walk ids from one atomic per wave, lane offsets
+// from mbcnt over the ballot), closest Dirichlet point and epsilon-shell
+// test, closest Neumann silhouette -> radius, guided direction (network on
+// MFMA for 64 walks at a time), Neumann sample and its visibility, source
+// point and its visibility, first hit in the star.  Inside a query phase a
+// lane whose traversal has finished takes the next walk of that phase's
+// list, so the wave does not wait for its slowest lane.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
