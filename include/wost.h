@@ -20,7 +20,8 @@
  *   Host pointers are only read during the call unless stated otherwise.
  * - Streams: `stream` is a hipStream_t passed as void* (NULL = default
  *   stream).  Launches are asynchronous on that stream; nothing synchronises
- *   except wost_build_bvh (host-only) and wost_geom_upload (host->device copy).
+ *   except wost_build_bvh (host-only), wost_build_bvh_device and wost_geom_upload
+ *   (which synchronise the stream they are given).
  * - Layouts: points and directions are row-major [n][dim] float32 (AoS).
  * - Handles are not thread-safe; distinct handles may be used concurrently.
  */
@@ -99,11 +100,37 @@ typedef struct {
 
 int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, const int32_t* prims,
                    int64_t n_prims, const uint8_t* bc, const wost_build_opts* opts, wost_geom** out);
+/* wost_build_bvh_device: the same build from device inputs, run on the GPU
+ * (the query library's hierarchies built in parallel, Sec. 5.3), giving the
+ * image wost_build_bvh gives byte for byte.
+ *   verts, prims, bc   device arrays, layouts as for wost_build_bvh
+ *   opts               NULL or leaf_size in 1..64; brute_force gives
+ *                      WOST_EUNSUPPORTED
+ *   workspace          device, 256-byte aligned, >= the bytes that
+ *                      wost_build_bvh_device_workspace reports (an upper
+ *                      bound from n_prims and leaf_size: about 0.7 KB per
+ *                      primitive in 2D and 1 KB in 3D)
+ *   stream             the build's kernels and copies; the call synchronises
+ *                      it several times and returns with it idle
+ * Invalid input gives WOST_EINVAL with the first offending vertex or
+ * primitive in the host builder's order; sets beyond 2^25 - 64 primitives or
+ * hierarchies deeper than the traversal stack give WOST_EUNSUPPORTED.  The
+ * built image stays in the workspace: wost_geom_upload copies it into the
+ * caller's buffer, so the workspace must stay untouched until that upload
+ * has returned; it may be freed or reused afterwards.  wost_geom_info and
+ * wost_geom_prim_index work on the handle at once. */
+int wost_build_bvh_device_workspace(int32_t dim, int64_t n_verts, int64_t n_prims, const wost_build_opts* opts,
+                                    int64_t* ws_bytes);
+int wost_build_bvh_device(int32_t dim, const float* verts, int64_t n_verts, const int32_t* prims, int64_t n_prims,
+                          const uint8_t* bc, const wost_build_opts* opts, void* workspace, int64_t ws_bytes,
+                          void* stream, wost_geom** out);
 /* Bytes of device memory the geometry needs (256-byte aligned base required). */
 int64_t wost_geom_device_bytes(const wost_geom* geom);
 /* Copy the geometry into the caller-owned device buffer `dev_buf` (>= bytes)
- * on `stream`, and synchronise that stream.  The buffer must outlive every
- * call that uses `geom`.  Re-uploading to another buffer is allowed. */
+ * on `stream`, and synchronise that stream: host to device for a host build,
+ * device to device (padding zeroed) for a device build.  The buffer must
+ * outlive every call that uses `geom`.  Re-uploading to another buffer is
+ * allowed. */
 int wost_geom_upload(wost_geom* geom, void* dev_buf, int64_t bytes, void* stream);
 /* Scene statistics: out[0..7] = dim, n_dirichlet, n_neumann, n_silhouette,
  * deepest binary split level, AABB diagonal, bytes, traversal stack entries

@@ -60,6 +60,9 @@ _F = C.c_float
 SIGNATURES = {
     "wost_last_error": (C.c_char_p, []),
     "wost_build_bvh": (_I, [_I32, _P, _I64, _P, _I64, _P, C.POINTER(wost_build_opts), C.POINTER(_P)]),
+    "wost_build_bvh_device_workspace": (_I, [_I32, _I64, _I64, C.POINTER(wost_build_opts), C.POINTER(_I64)]),
+    "wost_build_bvh_device": (_I, [_I32, _P, _I64, _P, _I64, _P, C.POINTER(wost_build_opts), _P, _I64, _P,
+                                   C.POINTER(_P)]),
     "wost_geom_device_bytes": (_I64, [_P]),
     "wost_geom_upload": (_I, [_P, _P, _I64, _P]),
     "wost_geom_info": (_I, [_P, C.POINTER(C.c_double)]),

@@ -48,30 +48,55 @@ def _field(desc, keep):
 
 
 class Geometry:
-    """Boundary hierarchies built on the host and uploaded into a torch buffer."""
+    """Boundary hierarchies in a torch buffer, built on the host
+    (``build="host"``, wost_build_bvh) or on the GPU from device copies of the
+    inputs (``build="gpu"``, wost_build_bvh_device); both give the same image."""
 
-    def __init__(self, dim, verts, prims, bc, leaf_size=4, brute_force=False, device=None):
+    def __init__(self, dim, verts, prims, bc, leaf_size=4, brute_force=False, device=None, build="host"):
         lib = L.load()
         self.dim = int(dim)
-        v = np.ascontiguousarray(verts, np.float32)
-        p = np.ascontiguousarray(prims, np.int32)
-        b = np.ascontiguousarray(bc, np.uint8)
         opts = L.wost_build_opts(int(leaf_size), 1 if brute_force else 0)
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         h = C.c_void_p()
-        L.check(lib.wost_build_bvh(self.dim, v.ctypes.data, v.shape[0], p.ctypes.data, p.shape[0], b.ctypes.data,
-                                   C.byref(opts), C.byref(h)), "wost_build_bvh")
+        ws = None
+        if build == "host":
+            v = np.ascontiguousarray(verts, np.float32)
+            p = np.ascontiguousarray(prims, np.int32)
+            b = np.ascontiguousarray(bc, np.uint8)
+            L.check(lib.wost_build_bvh(self.dim, v.ctypes.data, v.shape[0], p.ctypes.data, p.shape[0],
+                                       b.ctypes.data, C.byref(opts), C.byref(h)), "wost_build_bvh")
+        elif build == "gpu":
+            v = torch.as_tensor(np.ascontiguousarray(verts, np.float32), device=dev).contiguous()
+            p = torch.as_tensor(np.ascontiguousarray(prims, np.int32), device=dev).contiguous()
+            b = torch.as_tensor(np.ascontiguousarray(bc, np.uint8), device=dev).contiguous()
+            need = C.c_int64()
+            L.check(lib.wost_build_bvh_device_workspace(self.dim, v.shape[0], p.shape[0], C.byref(opts),
+                                                        C.byref(need)), "wost_build_bvh_device_workspace")
+            ws = torch.empty(need.value + 256, dtype=torch.uint8, device=dev)
+            ws_base = ws.data_ptr() + (-ws.data_ptr()) % 256
+            L.check(lib.wost_build_bvh_device(self.dim, v.data_ptr(), v.shape[0], p.data_ptr(), p.shape[0],
+                                              b.data_ptr(), C.byref(opts), C.c_void_p(ws_base), need.value,
+                                              _stream(), C.byref(h)), "wost_build_bvh_device")
+        else:
+            raise ValueError("build must be 'host' or 'gpu'")
         self.h = h
         nbytes = lib.wost_geom_device_bytes(h)
-        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         off = (-self.buf.data_ptr()) % 256
         self._base = self.buf.data_ptr() + off
+        self._off = off
+        self.nbytes = int(nbytes)
         L.check(lib.wost_geom_upload(h, C.c_void_p(self._base), nbytes, _stream()), "wost_geom_upload")
+        del ws
         info = (C.c_double * 8)()
         L.check(lib.wost_geom_info(h, info), "wost_geom_info")
         self.info = dict(dim=int(info[0]), n_dirichlet=int(info[1]), n_neumann=int(info[2]),
                          n_silhouette=int(info[3]), max_depth=int(info[4]), diag=float(info[5]),
                          bytes=int(info[6]))
+
+    def image(self):
+        """The uploaded device image as a uint8 tensor view."""
+        return self.buf[self._off:self._off + self.nbytes]
 
     @classmethod
     def from_scene(cls, scene, **kw):
@@ -148,6 +173,10 @@ class Problem:
         self.g, self.h, self.f = g, h, f
         self.eps, self.r_min, self.max_steps, self.rr_start, self.rr_q = eps, r_min, max_steps, rr_start, rr_q
         self.sampling, self.c_fixed, self.reflect = sampling, c_fixed, reflect
+
+    def image(self):
+        """The uploaded device image as a uint8 tensor view."""
+        return self.buf[self._off:self._off + self.nbytes]
 
     @classmethod
     def from_scene(cls, scene, **kw):

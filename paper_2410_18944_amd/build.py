@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwost.so")
-SOURCES = ["geom_build.cpp", "walk.hip", "wavefront.hip", "lbvh.hip", "guide.hip", "train.hip"]
+SOURCES = ["geom_build.cpp", "geom_gpu.hip", "walk.hip", "wavefront.hip", "lbvh.hip", "guide.hip", "train.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

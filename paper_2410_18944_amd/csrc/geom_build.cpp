@@ -89,6 +89,9 @@ struct Builder {
     {
         max_depth = std::max(max_depth, depth);
         if (e - b <= leaf) {
+            // a leaf lists its items by id, whatever order the splits left
+            std::sort(items->begin() + b, items->begin() + e,
+                      [](const Item& p, const Item& q) { return p.id < q.id; });
             out_c = (int32_t)order.size();
             out_n = e - b;
             for (int i = b; i < e; ++i) order.push_back((*items)[i].id);
@@ -162,24 +165,6 @@ int64_t push_bytes(std::vector<uint8_t>& img, const T* data, size_t count)
     img.resize(off + sizeof(T) * count);
     if (count) memcpy(img.data() + off, data, sizeof(T) * count);
     return (int64_t)off;
-}
-
-// cone of a set of unit vectors: (axis, half-angle); pi if undefined
-void cone_of(const std::vector<std::array<double, 3>>& v, int d, double axis[3], double& half)
-{
-    double s[3] = {0, 0, 0};
-    for (auto& n : v)
-        for (int i = 0; i < d; ++i) s[i] += n[i];
-    double len = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-    if (v.empty() || len < 1e-9 * v.size()) {
-        axis[0] = 1; axis[1] = 0; axis[2] = 0;
-        half = M_PI;
-        return;
-    }
-    for (int i = 0; i < 3; ++i) axis[i] = s[i] / len;
-    double worst = 1.0;
-    for (auto& n : v) worst = std::min(worst, axis[0] * n[0] + axis[1] * n[1] + axis[2] * n[2]);
-    half = std::acos(std::max(-1.0, std::min(1.0, worst)));
 }
 
 }  // namespace
@@ -290,6 +275,7 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
         }
         all.add(p, d);
     }
+    for (int i = 0; i < 3; ++i) { all.lo[i] += 0.0; all.hi[i] += 0.0; }   // no negative zeros
     for (int64_t q = 0; q < n_prims; ++q) {
         if (bc[q] > 1) { set_error("wost_build_bvh: bc[%lld] must be 0 or 1", (long long)q); return WOST_EINVAL; }
         for (int k = 0; k < d; ++k) {
@@ -353,70 +339,62 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
             sils.push_back(s);
         }
     }
-    // ---- convex pieces (2D): maximal runs of Neumann segments joined at
-    // strictly convex vertices, cut so that each run turns by less than
-    // 0.9 pi.  Such a run is the graph of a convex function over some
+    // ---- convex pieces (2D).  A vertex shared by exactly two Neumann
+    // segments links them when it is strictly convex, one segment ends where
+    // the other starts, and both outward normals lie in the same closed
+    // quadrant.  A piece is a maximal chain of links: its normals turn one
+    // way by at most pi/2, so it is the graph of a convex function over some
     // direction and lies on the domain side of every one of its segments'
-    // lines, so seen from a point on one of its segments every segment of
-    // the run faces front and no vertex interior to it is a silhouette.
+    // lines.  Seen from a point on one of its segments every segment of the
+    // piece faces front, and no vertex interior to it is a silhouette.  A
+    // piece is named by the caller index of its last segment, found by
+    // pointer jumping along the links for a fixed number of rounds (a closed
+    // chain, impossible for these turns, would only split into more names).
     std::vector<int32_t> seg_piece(n_prims, -1);
+    std::vector<char> link(d == 2 ? n_verts : 0, 0);
     if (d == 2) {
         std::vector<std::vector<int64_t>> inc(n_verts);
         for (int64_t q = 0; q < n_prims; ++q)
             if (bc[q])
                 for (int k = 0; k < 2; ++k) inc[prims[q * 2 + k]].push_back(q);
-        auto other_end = [&](int64_t q, int64_t v) { return prims[q * 2] == v ? prims[q * 2 + 1] : prims[q * 2]; };
-        std::vector<char> join(n_verts, 0);
-        std::vector<double> turn(n_verts, 0.0);
+        auto quadrant = [&](int64_t q) {
+            return nout[q][0] >= 0 ? (nout[q][1] >= 0 ? 0 : 3) : (nout[q][1] >= 0 ? 1 : 2);
+        };
+        std::vector<int64_t> jump(n_prims, -1), jump2(n_prims, -1);
+        int64_t n_neu_segs = 0;
+        for (int64_t q = 0; q < n_prims; ++q)
+            if (bc[q]) { jump[q] = q; ++n_neu_segs; }
         for (int64_t v = 0; v < n_verts; ++v) {
             if (inc[v].size() != 2) continue;
             const int64_t s1 = inc[v][0], s2 = inc[v][1];
-            const int64_t p1 = other_end(s1, v), p2 = other_end(s2, v);
-            if (p1 == v || p2 == v) continue;
+            const bool end1 = prims[s1 * 2 + 1] == v, end2 = prims[s2 * 2 + 1] == v;
+            if (end1 == end2) continue;
+            const int64_t p1 = end1 ? prims[s1 * 2] : prims[s1 * 2 + 1];
+            const int64_t p2 = end2 ? prims[s2 * 2] : prims[s2 * 2 + 1];
             double e1[2], e2[2];
             for (int i = 0; i < 2; ++i) {
-                e1[i] = (double)verts[p1 * 2 + i] - verts[v * 2 + i];
-                e2[i] = (double)verts[p2 * 2 + i] - verts[v * 2 + i];
+                e1[i] = (double)verts[p1 * 2 + i] - (double)verts[v * 2 + i];
+                e2[i] = (double)verts[p2 * 2 + i] - (double)verts[v * 2 + i];
             }
-            const double l1 = std::hypot(e1[0], e1[1]), l2 = std::hypot(e2[0], e2[1]);
-            // sine of the turn, measured against each inward normal
+            const double l1 = std::sqrt(e1[0] * e1[0] + e1[1] * e1[1]);
+            const double l2 = std::sqrt(e2[0] * e2[0] + e2[1] * e2[1]);
+            // sine of the turn, measured against each outward normal
             const double c1 = -(e2[0] * nout[s1][0] + e2[1] * nout[s1][1]) / l2;
             const double c2 = -(e1[0] * nout[s2][0] + e1[1] * nout[s2][1]) / l1;
-            if (!(c1 > 1e-6 && c2 > 1e-6)) continue;
-            join[v] = 1;
-            turn[v] = std::acos(std::max(-1.0, std::min(1.0, -(e1[0] * e2[0] + e1[1] * e2[1]) / (l1 * l2))));
+            if (!(c1 > 1e-6 && c2 > 1e-6) || quadrant(s1) != quadrant(s2)) continue;
+            link[v] = 1;
+            if (end1) jump[s1] = s2;
+            else jump[s2] = s1;
         }
-        const double limit = 0.9 * M_PI;
-        int32_t n_pieces = 0;
-        for (int64_t q0 = 0; q0 < n_prims; ++q0) {
-            if (!bc[q0] || seg_piece[q0] >= 0) continue;
-            // back up to the first segment of the run (or stay on q0 for a
-            // closed convex loop)
-            int64_t cur = q0, v = prims[q0 * 2];
-            for (int64_t guard = 0; guard < n_prims && join[v]; ++guard) {
-                const int64_t prv = inc[v][0] == cur ? inc[v][1] : inc[v][0];
-                if (prv == q0 || seg_piece[prv] >= 0) break;
-                cur = prv;
-                v = other_end(prv, v);
-            }
-            // walk forward, starting a new piece whenever the turn would
-            // reach the limit
-            int32_t pc = n_pieces++;
-            double acc = 0.0;
-            seg_piece[cur] = pc;
-            v = other_end(cur, v);
-            for (int64_t guard = 0; guard < n_prims && join[v]; ++guard) {
-                const int64_t nxt = inc[v][0] == cur ? inc[v][1] : inc[v][0];
-                if (seg_piece[nxt] >= 0) break;
-                if (acc + turn[v] >= limit) { pc = n_pieces++; acc = 0.0; }
-                else acc += turn[v];
-                seg_piece[nxt] = pc;
-                cur = nxt;
-                v = other_end(nxt, v);
-            }
+        int rounds = 1;
+        while ((int64_t(1) << rounds) < n_neu_segs + 1) ++rounds;
+        for (int r = 0; r < rounds; ++r) {
+            for (int64_t q = 0; q < n_prims; ++q) jump2[q] = jump[q] >= 0 ? jump[jump[q]] : -1;
+            jump.swap(jump2);
         }
+        for (int64_t q = 0; q < n_prims; ++q) seg_piece[q] = bc[q] ? (int32_t)jump[q] : -1;
         for (auto& sl : sils)
-            if (!sl.boundary && join[sl.v] && seg_piece[sl.q1] == seg_piece[sl.q2]) sl.piece = seg_piece[sl.q1];
+            if (link[sl.v]) sl.piece = seg_piece[sl.q1];
     }
     // ---- hierarchies
     wost_geom* g = new wost_geom();
@@ -485,69 +463,99 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
                 return WOST_EINVAL;
             }
         }
-        // aggregates per node child: measure (Neumann) or normal cone (silhouettes)
-        std::vector<double> sub_meas(nn * 2, 0.0);
-        std::vector<std::array<double, 4>> sub_cone(nn * 2, {1, 0, 0, M_PI});
-        // iterate nodes in reverse creation order: children are created after parents
-        std::vector<double> node_meas(nn, 0.0);
-        std::vector<std::vector<std::array<double, 3>>> node_normals(which == 2 ? nn : 0);
-        std::vector<char> node_has_boundary(nn, 0);
-        // convex piece shared by every candidate of a subtree, or -1
+        // aggregates per node child, bottom-up (children are created after
+        // their parents): the Neumann measure of the subtree; for
+        // silhouettes the sum of the candidates' normals (a leaf adds its
+        // candidates' normals in leaf order, an inner child copies its node's
+        // sum, and a node adds its two children's sums), how many normals,
+        // whether a boundary feature lies below, and the convex piece all
+        // candidates share
+        std::vector<double> sub_meas(nn * 2, 0.0), node_meas(nn, 0.0);
+        std::vector<std::array<double, 3>> sub_sum(which == 2 ? nn * 2 : 0), node_sum(which == 2 ? nn : 0);
+        std::vector<int64_t> sub_cnt(which == 2 ? nn * 2 : 0, 0), node_cnt(which == 2 ? nn : 0, 0);
+        std::vector<char> sub_bnd(which == 2 ? nn * 2 : 0, 0), node_bnd(which == 2 ? nn : 0, 0);
+        // leaf-order range [first, first + count) of every child
+        std::vector<int32_t> sub_first(nn * 2, 0), sub_count(nn * 2, 0), node_first(nn, 0), node_count(nn, 0);
         std::vector<int32_t> sub_piece(nn * 2, -1), node_piece(nn, -1);
         auto join_piece = [](int32_t a, int32_t b) { return a == -2 ? b : (b == -2 ? a : (a == b ? a : -1)); };
         for (int ni = nn - 1; ni >= 0; --ni) {
             const BuiltNode& nd = B.nodes[ni];
             int32_t np_acc = -2;
+            double nsum[3] = {0.0, 0.0, 0.0};
             for (int ch = 0; ch < 2; ++ch) {
-                if (which == 2) {
-                    int32_t pc = -2;
-                    if (nd.n[ch] > 0)
-                        for (int k = nd.c[ch]; k < nd.c[ch] + nd.n[ch]; ++k) pc = join_piece(pc, sils[B.order[k]].piece);
-                    else if (nd.c[ch] >= 0)
-                        pc = node_piece[nd.c[ch]];
-                    sub_piece[ni * 2 + ch] = pc == -2 ? -1 : pc;
-                    np_acc = join_piece(np_acc, pc);
-                }
+                const int k2 = ni * 2 + ch;
                 double m = 0;
-                std::vector<std::array<double, 3>> normals;
+                double ssum[3] = {0.0, 0.0, 0.0};
+                int64_t cnt = 0;
                 bool bnd = false;
-                if (nd.c[ch] < 0 && nd.n[ch] == 0) {
-                    // empty
-                } else if (nd.n[ch] > 0) {
+                int32_t pc = -2;
+                if (nd.n[ch] > 0) {
+                    sub_first[k2] = nd.c[ch];
+                    sub_count[k2] = nd.n[ch];
                     for (int k = nd.c[ch]; k < nd.c[ch] + nd.n[ch]; ++k) {
-                        int32_t id = B.order[k];
+                        const int32_t id = B.order[k];
                         if (which == 1) m += meas[id];
                         if (which == 2) {
-                            const Sil& s = sils[id];
-                            normals.push_back({s.n1[0], s.n1[1], s.n1[2]});
-                            if (!s.boundary) normals.push_back({s.n2[0], s.n2[1], s.n2[2]});
-                            bnd = bnd || s.boundary;
+                            const Sil& sl = sils[id];
+                            for (int i = 0; i < 3; ++i) ssum[i] += sl.n1[i];
+                            ++cnt;
+                            if (!sl.boundary) {
+                                for (int i = 0; i < 3; ++i) ssum[i] += sl.n2[i];
+                                ++cnt;
+                            }
+                            bnd = bnd || sl.boundary;
+                            pc = join_piece(pc, sl.piece);
                         }
                     }
-                } else {
-                    int c = nd.c[ch];
+                } else if (nd.c[ch] >= 0) {
+                    const int c = nd.c[ch];
+                    sub_first[k2] = node_first[c];
+                    sub_count[k2] = node_count[c];
                     m = node_meas[c];
                     if (which == 2) {
-                        normals = node_normals[c];
-                        bnd = node_has_boundary[c];
+                        for (int i = 0; i < 3; ++i) ssum[i] = node_sum[c][i];
+                        cnt = node_cnt[c];
+                        bnd = node_bnd[c];
+                        pc = node_piece[c];
                     }
                 }
-                sub_meas[ni * 2 + ch] = m;
+                sub_meas[k2] = m;
                 node_meas[ni] += m;
+                node_count[ni] += sub_count[k2];
                 if (which == 2) {
-                    double ax[3], half;
-                    cone_of(normals, d, ax, half);
-                    if (bnd) half = M_PI;
-                    sub_cone[ni * 2 + ch] = {ax[0], ax[1], ax[2], half};
-                    node_normals[ni].insert(node_normals[ni].end(), normals.begin(), normals.end());
-                    node_has_boundary[ni] = node_has_boundary[ni] || bnd;
+                    for (int i = 0; i < 3; ++i) { sub_sum[k2][i] = ssum[i]; nsum[i] += ssum[i]; }
+                    sub_cnt[k2] = cnt;
+                    sub_bnd[k2] = bnd;
+                    sub_piece[k2] = pc == -2 ? -1 : pc;
+                    node_cnt[ni] += cnt;
+                    node_bnd[ni] = node_bnd[ni] || bnd;
+                    np_acc = join_piece(np_acc, pc);
                 }
             }
-            if (which == 2) node_piece[ni] = np_acc == -2 ? -1 : np_acc;
+            node_first[ni] = sub_first[ni * 2];
             if (which == 2) {
-                // keep memory bounded: children's lists are no longer needed
-                for (int ch = 0; ch < 2; ++ch)
-                    if (nd.n[ch] == 0 && nd.c[ch] >= 0) std::vector<std::array<double, 3>>().swap(node_normals[nd.c[ch]]);
+                for (int i = 0; i < 3; ++i) node_sum[ni][i] = nsum[i];
+                node_piece[ni] = np_acc == -2 ? -1 : np_acc;
+            }
+        }
+        // normal cone of every child: axis = normalised normal sum, and the
+        // cosine of its half-angle = the smallest cosine between the axis and
+        // any normal below (from 1); undefined sums give the axis (1, 0, 0)
+        // and a cone that never culls
+        std::vector<std::array<double, 4>> sub_cone(which == 2 ? nn * 2 : 0, {1.0, 0.0, 0.0, -1.0});
+        if (which == 2) {
+            for (int k2 = 0; k2 < nn * 2; ++k2) {
+                const auto& sm = sub_sum[k2];
+                const double len = std::sqrt(sm[0] * sm[0] + sm[1] * sm[1] + sm[2] * sm[2]);
+                if (sub_cnt[k2] == 0 || len < 1e-9 * (double)sub_cnt[k2]) continue;
+                const double ax[3] = {sm[0] / len, sm[1] / len, sm[2] / len};
+                double worst = 1.0;
+                for (int k = sub_first[k2]; k < sub_first[k2] + sub_count[k2]; ++k) {
+                    const Sil& sl = sils[B.order[k]];
+                    worst = std::min(worst, ax[0] * sl.n1[0] + ax[1] * sl.n1[1] + ax[2] * sl.n1[2]);
+                    if (!sl.boundary) worst = std::min(worst, ax[0] * sl.n2[0] + ax[1] * sl.n2[1] + ax[2] * sl.n2[2]);
+                }
+                sub_cone[k2] = {ax[0], ax[1], ax[2], worst};
             }
         }
         // ---- serialise
@@ -560,12 +568,12 @@ extern "C" int wost_build_bvh(int32_t dim, const float* verts, int64_t n_verts, 
             if (which == 1) return make_float4((float)sub_meas[ni * 2 + ch], 0.f, 0.f, 0.f);
             if (which == 2) {
                 // normal cone as (axis, cos of the half-angle); cos <= 0 marks
-                // a cone that never culls (half-angle >= pi/2, or a subtree
-                // holding a boundary feature).  The cosine is rounded down so
-                // the stored cone contains the exact one.
+                // a cone that never culls (half-angle >= pi/2, an undefined
+                // axis, or a subtree holding a boundary feature).  The cosine
+                // is rounded down so the stored cone contains the exact one.
                 auto& c = sub_cone[ni * 2 + ch];
-                const double ch_ = std::cos(c[3]);
-                const float cw = (c[3] >= 0.5 * M_PI || brute) ? -1.f : std::nextafter((float)ch_, -INFINITY);
+                const bool off = brute || sub_bnd[ni * 2 + ch] || !(c[3] > 0.0);
+                const float cw = off ? -1.f : std::nextafter((float)c[3], -INFINITY);
                 return make_float4((float)c[0], (float)c[1], (float)c[2], cw);
             }
             return make_float4(0.f, 0.f, 0.f, 0.f);
@@ -761,7 +769,16 @@ extern "C" int wost_geom_upload(wost_geom* g, void* dev_buf, int64_t bytes, void
     if (bytes < g->bytes) { set_error("wost_geom_upload: buffer has %lld bytes, need %lld", (long long)bytes, (long long)g->bytes); return WOST_ESIZE; }
     if (((uintptr_t)dev_buf) & 255) { set_error("wost_geom_upload: buffer must be 256-byte aligned"); return WOST_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemcpyAsync(dev_buf, g->image, g->bytes, hipMemcpyHostToDevice, s);
+    hipError_t e = hipSuccess;
+    if (g->image) {
+        e = hipMemcpyAsync(dev_buf, g->image, g->bytes, hipMemcpyHostToDevice, s);
+    } else {
+        // device-built: padding zeroed as in the host image, then every array
+        e = hipMemsetAsync(dev_buf, 0, g->bytes, s);
+        for (size_t k = 0; k < g->staged.size() && e == hipSuccess; ++k)
+            e = hipMemcpyAsync((uint8_t*)dev_buf + g->staged[k].off, g->staged[k].src, g->staged[k].bytes,
+                               hipMemcpyDeviceToDevice, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { set_error("wost_geom_upload: %s", hipGetErrorString(e)); return WOST_EHIP; }
     g->dev = dev_buf;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/wost.h"
 
 namespace wost {
@@ -109,6 +111,10 @@ struct wost_geom {
         const int32_t* orig = nullptr;
         int32_t n_nodes = 0, n_prims = 0, stack = 0;
     } dir_dev;
+    // a geometry built on the device: the image's arrays as they lie in the
+    // build workspace, copied to their offsets by wost_geom_upload
+    struct Staged { const void* src; int64_t off, bytes; };
+    std::vector<Staged> staged;
     wost::DevGeom devgeom() const;
     // traversal stack entries a lane needs with the hierarchies in use
     int32_t stack_need() const { return dir_dev.nodes && dir_dev.stack > stack_entries ? dir_dev.stack : stack_entries; }

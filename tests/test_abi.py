@@ -215,3 +215,30 @@ def test_guide_create_validates_config(lib):
         cfg = GuideConfig(**{**good.__dict__, **bad})
         c = cfg.to_c()
         assert L.wost_guide_create(C.byref(c), C.byref(h)) < 0
+
+
+def test_device_build_workspace_validates_and_scales(lib):
+    """The device build's size query and argument checks run on the host
+    (no kernel is launched before they pass)."""
+    L = lib.load()
+    ws = C.c_int64()
+    opts = lib.wost_build_opts(4, 0)
+    assert L.wost_build_bvh_device_workspace(4, 10, 10, None, C.byref(ws)) == -1
+    assert L.wost_build_bvh_device_workspace(2, 10, 0, None, C.byref(ws)) == -1
+    assert L.wost_build_bvh_device_workspace(2, 10, 10, C.byref(lib.wost_build_opts(0, 0)), C.byref(ws)) == -1
+    assert L.wost_build_bvh_device_workspace(2, 10, 1 << 26, None, C.byref(ws)) < 0
+    sizes = []
+    for n in (1, 100, 10000):
+        assert L.wost_build_bvh_device_workspace(3, 3 * n, n, C.byref(opts), C.byref(ws)) == 0
+        sizes.append(ws.value)
+    assert sizes[0] > 0 and sizes[0] < sizes[1] < sizes[2]
+    assert sizes[2] < 2000 * 10000   # linear, about 1 KB per triangle
+    h = C.c_void_p()
+    fake = C.c_void_p(4096)
+    assert L.wost_build_bvh_device(2, None, 10, fake, 10, fake, None, fake, 1 << 30, None, C.byref(h)) == -1
+    assert L.wost_build_bvh_device(2, fake, 10, fake, 10, fake, C.byref(lib.wost_build_opts(4, 1)), fake, 1 << 30,
+                                   None, C.byref(h)) < 0
+    assert L.wost_build_bvh_device(2, fake, 10, fake, 10, fake, None, fake, 16, None, C.byref(h)) == -2
+    assert L.wost_build_bvh_device(2, fake, 10, fake, 10, fake, None, C.c_void_p(4096 + 8), 1 << 30, None,
+                                   C.byref(h)) == -1
+    assert not h.value
