@@ -426,7 +426,7 @@ int wost_guide_train_step(wost_guide* g, const wost_records* rec, int64_t begin,
  * (wost_guide_train_workspace_bytes(g, count) > WOST_NOALLOC_SCRATCH_BYTES;
  * 2^18 records fit for the 2D and 3D guides of the benchmark scenes).  Other
  * arguments and errors as wost_guide_train_step. */
-#define WOST_NOALLOC_SCRATCH_BYTES (64ll << 20)
+#define WOST_NOALLOC_SCRATCH_BYTES (128ll << 20)
 int wost_guide_train_step_noalloc(wost_guide* g, const wost_records* rec, int64_t begin, int64_t count,
                                   const wost_adam* opt, float* loss_out, void* stream);
 

@@ -44,8 +44,8 @@ struct TrainArgs {
     float* partials;        // [gridDim.x][n_frag] weight gradients in MFMA fragment order
     int32_t n_frag;         // floats per workgroup row (= 256 x weight-gradient blocks)
     int32_t blk_off[kMaxLayers];   // first 16x16 block of each layer in a row
-    float* gco;             // coarse-level feature gradients [2 n_coarse][count]
-    int32_t n_coarse;       // levels below this are staged in gco, not scattered
+    float* gco;             // per-record feature gradients of every level [2 L][count]
+    uint32_t* gmax;         // [L] largest |feature gradient| of each level (float bits)
     int32_t backward;
     int32_t p_mlp;
     int32_t off[kMaxLayers];   // layer weight offsets relative to the MLP start
@@ -239,6 +239,7 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
 
     const int64_t n_tiles = (a.count + 63) / 64;
     float loss_acc = 0.f;
+    float gmx[4][2] = {{0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}, {0.f, 0.f}};   // per owned level
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t i = tile * 64 + lane;
         const bool valid = i < a.count;
@@ -419,7 +420,8 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
                 __syncthreads();
                 _Float16* t = cur; cur = nxt; nxt = t;
             } else {
-                // grid scatter: this lane owns levels 8 mb + 2 g4 + {0,1} of walk 16 cb + col
+                // feature gradients, staged per record for slice_scatter_kernel:
+                // this lane owns levels 8 mb + 2 g4 + {0,1} of walk 16 cb + col
                 const float inv = 1.f / Sc;
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb) {
@@ -436,53 +438,11 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
                         for (int lv = 0; lv < 2; ++lv) {
                             const int l = 8 * mb + 2 * g4 + lv;
                             const float gf0 = dz[cb][mb][2 * lv] * inv, gf1 = dz[cb][mb][2 * lv + 1] * inv;
-                            if (l < a.n_coarse) {
-                                // coarse levels: staged per record, scattered by coarse_scatter_kernel
-                                if (wvalid) {
-                                    const int64_t iw = tile * 64 + w;
-                                    a.gco[(int64_t)(2 * l) * a.count + iw] = gf0;
-                                    a.gco[(int64_t)(2 * l + 1) * a.count + iw] = gf1;
-                                }
-                                continue;
-                            }
-                            if (!wvalid || (gf0 == 0.f && gf1 == 0.f)) continue;
-                            const int N = g.res[l];
-                            int cc[D];
-                            float fr[D];
-#pragma unroll
-                            for (int d = 0; d < D; ++d) {
-                                const float pos = xh[d] * (float)N;
-                                int ci = (int)floorf(pos);
-                                ci = min(max(ci, 0), N - 1);
-                                cc[d] = ci;
-                                fr[d] = pos - (float)ci;
-                            }
-                            float* gl = a.grad + (int64_t)l * T * 2;
-#pragma unroll
-                            for (int corner = 0; corner < (1 << D); ++corner) {
-                                float wt = 1.f;
-                                uint32_t idx = 0;
-                                if (g.dense[l]) {
-                                    uint32_t stride = 1;
-#pragma unroll
-                                    for (int d = 0; d < D; ++d) {
-                                        const int b = (corner >> d) & 1;
-                                        wt *= b ? fr[d] : 1.f - fr[d];
-                                        idx += (uint32_t)(cc[d] + b) * stride;
-                                        stride *= (uint32_t)(N + 1);
-                                    }
-                                } else {
-                                    const uint32_t primes[3] = {1u, 2654435761u, 805459861u};
-#pragma unroll
-                                    for (int d = 0; d < D; ++d) {
-                                        const int b = (corner >> d) & 1;
-                                        wt *= b ? fr[d] : 1.f - fr[d];
-                                        idx ^= (uint32_t)(cc[d] + b) * primes[d];
-                                    }
-                                    idx &= (uint32_t)(T - 1);
-                                }
-                                atomicAdd(gl + 2 * (int64_t)idx, wt * gf0);
-                                atomicAdd(gl + 2 * (int64_t)idx + 1, wt * gf1);
+                            if (wvalid) {
+                                const int64_t iw = tile * 64 + w;
+                                a.gco[(int64_t)(2 * l) * a.count + iw] = gf0;
+                                a.gco[(int64_t)(2 * l + 1) * a.count + iw] = gf1;
+                                gmx[mb][lv] = fmaxf(gmx[mb][lv], fmaxf(fabsf(gf0), fabsf(gf1)));
                             }
                         }
                     }
@@ -495,82 +455,194 @@ __global__ __launch_bounds__(64) void train_kernel(const GuideDev g, const Train
         const float s = wave_sum(loss_acc);
         if (lane == 0) atomicAdd(a.loss_sum, s * a.loss_scale);
     }
+    if (a.backward) {
+        // the 16 lanes of a group own the same levels: reduce, one atomic each
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+            if (mb >= kb0) break;
+#pragma unroll
+            for (int lv = 0; lv < 2; ++lv) {
+                float m = gmx[mb][lv];
+                for (int o = 8; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+                if (col == 0 && m > 0.f) atomicMax(&a.gmax[8 * mb + 2 * g4 + lv], __float_as_uint(m));
+            }
+        }
+    }
 }
 
-// grad[mlp] += sum over workgroup partials, fixed order (deterministic)
-// Feature gradients of the coarse dense levels: every record touches the same
-// few thousand cells, so scattering them with global atomics serialises on a
-// handful of addresses.  Each workgroup accumulates its share of the records
-// into a private LDS copy of those levels (LDS fp32 atomics) and then adds
-// the non-zero entries to the gradient once.
+// Feature gradients of the grid levels, without global atomics.  A workgroup
+// owns a slice of kSliceEntries consecutive entries of one level's table and
+// adds, over its share of the records, every corner contribution that falls
+// in its slice.  It accumulates in LDS in 64-bit fixed point (integer LDS
+// atomics run far faster than fp32 ones, and integer sums do not depend on
+// their order): the scale 2^k keeps the share's largest possible sum, records
+// x the level's largest |feature gradient|, below 2^62.  With one share per
+// slice it then adds the slice to the gradient with plain loads and stores
+// (no other workgroup writes those entries); with R shares it writes its
+// partial slice and slice_reduce_kernel adds the R partials.  A workgroup
+// reads its records four per thread in flight; dense levels skip records
+// whose corners all miss the slice.
+constexpr int kSliceEntries = 10240;   // 160 KB of LDS
+constexpr int kSliceThreads = 1024;
+constexpr int kSliceUnroll = 4;
+
+struct SliceTab {
+    int32_t n;                      // rows: one per level
+    int32_t level[kMaxLevels];
+    int32_t entries[kMaxLevels];    // table entries of the level
+    int32_t shares[kMaxLevels];     // record shares R of each slice of the row
+    int32_t first[kMaxLevels + 1];  // first workgroup of each row; first[n] = workgroups
+    int64_t poff[kMaxLevels + 1];   // first float of each row's partials (R > 1 rows); poff[n] = floats
+};
+
 template <int D>
-__global__ __launch_bounds__(512) void coarse_scatter_kernel(const GuideDev g, const float* rec, int64_t cap,
-                                                             int64_t begin, int64_t count, const float* gco,
-                                                             int n_coarse, float* grad)
+__global__ __launch_bounds__(kSliceThreads) void slice_scatter_kernel(const GuideDev g, const float* rec, int64_t cap,
+                                                                      int64_t begin, int64_t count, const float* gco,
+                                                                      const uint32_t* gmax, const SliceTab st,
+                                                                      float* grad, float* partial)
 {
-    extern __shared__ float s_g[];
-    int total = 0;
-    for (int l = 0; l < n_coarse; ++l) {
-        int cells = 1;
-        for (int d = 0; d < D; ++d) cells *= g.res[l] + 1;
-        total += 2 * cells;
-    }
-    for (int j = threadIdx.x; j < total; j += blockDim.x) s_g[j] = 0.f;
+    extern __shared__ unsigned long long s_q[];
+    int k = 0;
+    while (k + 1 < st.n && (int)blockIdx.x >= st.first[k + 1]) ++k;
+    const int R = st.shares[k];
+    const int wg = (int)blockIdx.x - st.first[k];
+    const int slice = wg / R, share = wg % R;
+    const int l = st.level[k];
+    const uint32_t lo = (uint32_t)slice * (uint32_t)kSliceEntries;
+    const uint32_t n_here = min((uint32_t)kSliceEntries, (uint32_t)st.entries[k] - lo);
+    for (uint32_t j = threadIdx.x; j < 2 * n_here; j += blockDim.x) s_q[j] = 0ull;
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
-        float x[D], xh[D];
+    const int64_t r_lo = count * share / R, r_hi = count * (share + 1) / R;
+    // fixed-point scale: |sum| <= (r_hi - r_lo) * gm < 2^(e + cn) <= 2^61
+    const float gm = __uint_as_float(gmax[l]);
+    int e = 0;
+    (void)frexpf(gm, &e);
+    int cn = 0;
+    while ((int64_t(1) << cn) < r_hi - r_lo) ++cn;
+    const int ks = 61 - e - cn;
+    const int N = g.res[l];
+    const bool dense = g.dense[l] != 0;
+    const uint32_t mask = (uint32_t)((1ll << g.log2T) - 1);
+    const float* g0 = gco + (int64_t)(2 * l) * count;
+    const float* g1 = gco + (int64_t)(2 * l + 1) * count;
+    const int64_t step = (int64_t)blockDim.x * kSliceUnroll;
+    // positions of the next group of records are fetched while the current
+    // group is processed
+    float xn[kSliceUnroll][D];
+    auto fetch = [&](int64_t b0) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) x[d] = rec[(int64_t)d * cap + begin + i];
-        normalise_input<D>(g, x, xh);
-        int lo = 0;
-        for (int l = 0; l < n_coarse; ++l) {
-            const int N = g.res[l];
-            const float gf0 = gco[(int64_t)(2 * l) * count + i], gf1 = gco[(int64_t)(2 * l + 1) * count + i];
-            int cells = 1;
-            for (int d = 0; d < D; ++d) cells *= N + 1;
-            if (gf0 != 0.f || gf1 != 0.f) {
-                int cc[D];
-                float fr[D];
+        for (int u = 0; u < kSliceUnroll; ++u) {
+            const int64_t i = max(r_lo, min(b0 + (int64_t)u * blockDim.x, r_hi - 1));
+#pragma unroll
+            for (int d = 0; d < D; ++d) xn[u][d] = rec[(int64_t)d * cap + begin + i];
+        }
+    };
+    if (gm > 0.f) fetch(r_lo + threadIdx.x);
+    for (int64_t base = r_lo + threadIdx.x; gm > 0.f && base < r_hi; base += step) {
+        float x[kSliceUnroll][D];
+#pragma unroll
+        for (int u = 0; u < kSliceUnroll; ++u)
+#pragma unroll
+            for (int d = 0; d < D; ++d) x[u][d] = xn[u][d];
+        if (base + step < r_hi) fetch(base + step);
+        // corners of every record of the group, then the gradients of the
+        // records with a corner in the slice (one round of loads), then the
+        // LDS sums
+        uint32_t rel[kSliceUnroll][1 << D];
+        float fr[kSliceUnroll][D];
+        bool hit[kSliceUnroll];
+#pragma unroll
+        for (int u = 0; u < kSliceUnroll; ++u) {
+            float xh[D];
+            normalise_input<D>(g, x[u], xh);
+            int cc[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const float pos = xh[d] * (float)N;
+                int ci = (int)floorf(pos);
+                ci = min(max(ci, 0), N - 1);
+                cc[d] = ci;
+                fr[u][d] = pos - (float)ci;
+            }
+            // the corner indices (the forward gather's, grid_level)
+            uint32_t part[D][2];
+            uint32_t stride = 1;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const uint32_t prime = d == 0 ? 1u : (d == 1 ? 2654435761u : 805459861u);
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    part[d][b] = dense ? (uint32_t)(cc[d] + b) * stride : (uint32_t)(cc[d] + b) * prime;
+                stride *= (uint32_t)(N + 1);
+            }
+            bool any = false;
+#pragma unroll
+            for (int corner = 0; corner < (1 << D); ++corner) {
+                uint32_t idx = 0;
 #pragma unroll
                 for (int d = 0; d < D; ++d) {
-                    const float pos = xh[d] * (float)N;
-                    int ci = (int)floorf(pos);
-                    ci = min(max(ci, 0), N - 1);
-                    cc[d] = ci;
-                    fr[d] = pos - (float)ci;
+                    const uint32_t t = part[d][(corner >> d) & 1];
+                    idx = dense ? idx + t : idx ^ t;
                 }
+                if (!dense) idx &= mask;
+                rel[u][corner] = idx - lo;
+                any = any || rel[u][corner] < n_here;
+            }
+            hit[u] = any && base + (int64_t)u * blockDim.x < r_hi;
+        }
+        float f0[kSliceUnroll], f1[kSliceUnroll];
 #pragma unroll
-                for (int corner = 0; corner < (1 << D); ++corner) {
+        for (int u = 0; u < kSliceUnroll; ++u) {
+            const int64_t i = base + (int64_t)u * blockDim.x;
+            f0[u] = hit[u] ? ldexpf(g0[i], ks) : 0.f;
+            f1[u] = hit[u] ? ldexpf(g1[i], ks) : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kSliceUnroll; ++u) {
+            if (f0[u] == 0.f && f1[u] == 0.f) continue;
+#pragma unroll
+            for (int corner = 0; corner < (1 << D); ++corner) {
+                if (rel[u][corner] < n_here) {
                     float wt = 1.f;
-                    int idx = 0, st = 1;
 #pragma unroll
-                    for (int d = 0; d < D; ++d) {
-                        const int b = (corner >> d) & 1;
-                        wt *= b ? fr[d] : 1.f - fr[d];
-                        idx += (cc[d] + b) * st;
-                        st *= N + 1;
-                    }
-                    atomicAdd(&s_g[lo + 2 * idx], wt * gf0);
-                    atomicAdd(&s_g[lo + 2 * idx + 1], wt * gf1);
+                    for (int d = 0; d < D; ++d) wt *= (corner >> d) & 1 ? fr[u][d] : 1.f - fr[u][d];
+                    atomicAdd(&s_q[2 * rel[u][corner]], (unsigned long long)(long long)(wt * f0[u]));
+                    atomicAdd(&s_q[2 * rel[u][corner] + 1], (unsigned long long)(long long)(wt * f1[u]));
                 }
             }
-            lo += 2 * cells;
         }
     }
     __syncthreads();
-    const int64_t T = 1ll << g.log2T;
-    int lo = 0;
-    for (int l = 0; l < n_coarse; ++l) {
-        int cells = 1;
-        for (int d = 0; d < D; ++d) cells *= g.res[l] + 1;
-        float* gl = grad + (int64_t)l * T * 2;
-        for (int j = threadIdx.x; j < 2 * cells; j += blockDim.x) {
-            const float v = s_g[lo + j];
-            if (v != 0.f) atomicAdd(gl + j, v);
+    const double inv = ldexp(1.0, -ks);
+    if (R == 1) {
+        float* gl = grad + (int64_t)l * (1ll << g.log2T) * 2 + 2 * (int64_t)lo;
+        for (uint32_t j = threadIdx.x; j < 2 * n_here; j += blockDim.x) {
+            const long long q = (long long)s_q[j];
+            if (q != 0) gl[j] += (float)((double)q * inv);
         }
-        lo += 2 * cells;
+    } else {
+        float* pr = partial + st.poff[k] + (int64_t)share * 2 * st.entries[k] + 2 * (int64_t)lo;
+        for (uint32_t j = threadIdx.x; j < 2 * n_here; j += blockDim.x) pr[j] = (float)((double)(long long)s_q[j] * inv);
     }
+}
+
+// grad += the sum of the R partial rows of every level with R > 1
+__global__ __launch_bounds__(256) void slice_reduce_kernel(const GuideDev g, const SliceTab st, const float* partial,
+                                                           float* grad)
+{
+    const int64_t f = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int k = -1;
+    int64_t j = f;
+    for (int r = 0; r < st.n; ++r) {
+        if (st.shares[r] == 1) continue;
+        const int64_t n2 = 2 * (int64_t)st.entries[r];
+        if (j < n2) { k = r; break; }
+        j -= n2;
+    }
+    if (k < 0) return;
+    float v = 0.f;
+    for (int r = 0; r < st.shares[k]; ++r) v += partial[st.poff[k] + (int64_t)r * 2 * st.entries[k] + j];
+    if (v != 0.f) grad[(int64_t)st.level[k] * (1ll << g.log2T) * 2 + j] += v;
 }
 
 struct FragMap {
@@ -691,42 +763,64 @@ static int train_grid_cap()
     return 4 * g_train_cu;
 }
 
-// LDS budget of the coarse-level scatter: the longest prefix of dense levels
-// whose two features fit in it is staged and scattered through LDS.
-constexpr int64_t kCoarseLdsFloats = 24 * 1024;
-
-static int coarse_levels(const GuideDev& g)
+// one row per grid level (table: (res + 1)^dim cells when dense, 2^log2T
+// entries when hashed).  Each slice of a row gets R record shares so that a
+// workgroup meets about count x 2^dim / 16 corner contributions (uniformly
+// spread records assumed), and all R scale up until the workgroups about
+// fill the chip.
+static SliceTab slice_table(const GuideDev& g, int64_t count)
 {
+    SliceTab st;
+    memset(&st, 0, sizeof(st));
+    int64_t slices[kMaxLevels];
+    const double target = (double)(1 << g.dim) * (double)std::max<int64_t>(count, 1) / 16.0;
     int64_t total = 0;
-    int n = 0;
     for (int l = 0; l < g.L; ++l) {
-        if (!g.dense[l]) break;
-        int64_t cells = 1;
-        for (int d = 0; d < g.dim; ++d) cells *= g.res[l] + 1;
-        if (total + 2 * cells > kCoarseLdsFloats) break;
-        total += 2 * cells;
-        ++n;
+        int64_t e = 1ll << g.log2T;
+        if (g.dense[l]) {
+            e = 1;
+            for (int d = 0; d < g.dim; ++d) e *= g.res[l] + 1;
+        }
+        st.level[l] = l;
+        st.entries[l] = (int32_t)e;
+        slices[l] = (e + kSliceEntries - 1) / kSliceEntries;
+        const double hits = (double)(1 << g.dim) * (double)count * (double)std::min<int64_t>(e, kSliceEntries) / (double)e;
+        st.shares[l] = (int32_t)std::max(1.0, std::min(64.0, std::ceil(hits / target)));
+        total += slices[l] * st.shares[l];
     }
-    return n;
+    st.n = g.L;
+    const int64_t fill = train_grid_cap() / 4;
+    if (total > 0 && total < fill) {
+        const int64_t m = (fill + total - 1) / total;
+        for (int l = 0; l < st.n; ++l) st.shares[l] = (int32_t)std::min<int64_t>(64, st.shares[l] * m);
+    }
+    // shares never exceed the records
+    for (int l = 0; l < st.n; ++l) st.shares[l] = (int32_t)std::max<int64_t>(1, std::min<int64_t>(st.shares[l], count));
+    int64_t wg = 0, floats = 0;
+    for (int l = 0; l < st.n; ++l) {
+        st.first[l] = (int32_t)wg;
+        st.poff[l] = floats;
+        wg += slices[l] * st.shares[l];
+        if (st.shares[l] > 1) floats += (int64_t)st.shares[l] * 2 * st.entries[l];
+    }
+    st.first[st.n] = (int32_t)wg;
+    st.poff[st.n] = floats;
+    return st;
 }
 
-static int64_t coarse_lds_floats(const GuideDev& g, int n_coarse)
+// the partial slices of rows with R > 1, 256-byte aligned
+static int64_t slice_partial_bytes(const SliceTab& st)
 {
-    int64_t total = 0;
-    for (int l = 0; l < n_coarse; ++l) {
-        int64_t cells = 1;
-        for (int d = 0; d < g.dim; ++d) cells *= g.res[l] + 1;
-        total += 2 * cells;
-    }
-    return total;
+    return (st.poff[st.n] * 4 + 255) / 256 * 256;
 }
 
-static int coarse_scatter_grid(int64_t count)
+// floats of the reduction over rows with R > 1
+static int64_t slice_reduce_floats(const SliceTab& st)
 {
-    // about 2048 records per workgroup, at most half a workgroup per CU: the
-    // flush adds (grid x staged entries) global atomics
-    const int64_t want = (count + 2047) / 2048;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(want, std::max(1, train_grid_cap() / 8)));
+    int64_t f = 0;
+    for (int l = 0; l < st.n; ++l)
+        if (st.shares[l] > 1) f += 2 * (int64_t)st.entries[l];
+    return f;
 }
 
 // floats per workgroup row of weight-gradient partials: one 16x16 block per
@@ -807,14 +901,21 @@ static int launch_train(const wost_guide* gd, const wost_records* rec, int64_t b
     a.n_frag = blk * 256;
     const int64_t n_tiles = (count + 63) / 64;
     const int grid = (int)std::min<int64_t>(n_tiles, train_grid_cap());
+    SliceTab st;
+    memset(&st, 0, sizeof(st));
+    float* slice_part = nullptr;
     if (backward) {
         if (!grad) { set_error("guide training: no gradient buffer bound"); return WOST_ESTATE; }
-        a.n_coarse = coarse_levels(g);
         const int64_t part = train_ws_partials(gd, count);
-        const int64_t need = part + (int64_t)2 * a.n_coarse * count * 4;
+        st = slice_table(g, count);
+        const int64_t gco_bytes = ((int64_t)2 * g.L * count * 4 + 255) / 256 * 256;
+        const int64_t need = part + gco_bytes + 256 + slice_partial_bytes(st);
         if (!workspace || ws_bytes < need) { set_error("guide training: workspace %lld < %lld", (long long)ws_bytes, (long long)need); return WOST_ESIZE; }
         a.partials = (float*)workspace;
-        a.gco = a.n_coarse ? (float*)((char*)workspace + part) : nullptr;
+        a.gco = (float*)((char*)workspace + part);
+        a.gmax = (uint32_t*)((char*)workspace + part + gco_bytes);
+        slice_part = (float*)((char*)workspace + part + gco_bytes + 256);
+        hipLaunchKernelGGL(zero_f32_t, dim3(1), dim3(64), 0, s, (float*)a.gmax, (int64_t)g.L);
     }
     const size_t lds = train_lds_bytes(gd, backward);
     if (lds > 160 * 1024) { set_error("guide training: configuration needs %zu bytes of LDS", lds); return WOST_EUNSUPPORTED; }
@@ -826,16 +927,18 @@ static int launch_train(const wost_guide* gd, const wost_records* rec, int64_t b
         const int ry = std::min(grid, 32);
         hipLaunchKernelGGL(reduce_partials, dim3((a.n_frag / 4 + 255) / 256, ry), dim3(256), 0, s,
                            (const float*)a.partials, grid, a.n_frag, fm, grad + gd->n_grid);
-        if (a.n_coarse) {
-            const size_t cl = sizeof(float) * (size_t)coarse_lds_floats(g, a.n_coarse);
-            const int cg = coarse_scatter_grid(count);
-            if (g.dim == 2)
-                hipLaunchKernelGGL(coarse_scatter_kernel<2>, dim3(cg), dim3(512), cl, s, g, (const float*)a.rec, a.cap,
-                                   a.begin, a.count, (const float*)a.gco, a.n_coarse, grad);
-            else
-                hipLaunchKernelGGL(coarse_scatter_kernel<3>, dim3(cg), dim3(512), cl, s, g, (const float*)a.rec, a.cap,
-                                   a.begin, a.count, (const float*)a.gco, a.n_coarse, grad);
-        }
+        const size_t sl = sizeof(unsigned long long) * 2 * (size_t)kSliceEntries;
+        const dim3 sg((unsigned)st.first[st.n]);
+        if (g.dim == 2)
+            hipLaunchKernelGGL(slice_scatter_kernel<2>, sg, dim3(kSliceThreads), sl, s, g, (const float*)a.rec, a.cap,
+                               a.begin, a.count, (const float*)a.gco, (const uint32_t*)a.gmax, st, grad, slice_part);
+        else
+            hipLaunchKernelGGL(slice_scatter_kernel<3>, sg, dim3(kSliceThreads), sl, s, g, (const float*)a.rec, a.cap,
+                               a.begin, a.count, (const float*)a.gco, (const uint32_t*)a.gmax, st, grad, slice_part);
+        const int64_t rf = slice_reduce_floats(st);
+        if (rf > 0)
+            hipLaunchKernelGGL(slice_reduce_kernel, dim3((unsigned)((rf + 255) / 256)), dim3(256), 0, s, g, st,
+                               (const float*)slice_part, grad);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) { set_error("guide training: launch failed: %s", hipGetErrorString(e)); return WOST_EHIP; }
@@ -849,7 +952,8 @@ using namespace wost;
 extern "C" int64_t wost_guide_train_workspace_bytes(const wost_guide* g, int64_t count)
 {
     if (!g || count < 0) return -1;
-    return train_ws_partials(g, count) + (int64_t)2 * coarse_levels(g->dev) * count * 4 + 256;
+    return train_ws_partials(g, count) + ((int64_t)2 * g->dev.L * count * 4 + 255) / 256 * 256 + 256 +
+           slice_partial_bytes(slice_table(g->dev, count)) + 256;
 }
 
 extern "C" int wost_tail_pass(int32_t dim, const wost_records* rec, const float* walk_value, int64_t n_slots,
@@ -950,13 +1054,15 @@ extern "C" int wost_guide_train_step(wost_guide* g, const wost_records* rec, int
 namespace wost {
 
 // Workspace of wost_guide_train_step_noalloc: the per-workgroup weight-gradient
-// partials and the per-record coarse-level staging of one training step.  It
-// is a device-side array; its name in host code is not a device address, so
-// the host uses the address hipGetSymbolAddress returns for the current
-// device.  Every device that loads the library holds its own copy until the
-// process ends, and every call on a device reuses that device's copy (the
-// kernels overwrite what they read: each workgroup clears its own partial row
-// and every record writes its staging entries).
+// partials, the per-record feature-gradient staging, the per-level gradient
+// maxima and the partial slices of one training step.  It is a device-side
+// array; its name in host code is not a device address, so the host uses the
+// address hipGetSymbolAddress returns for the current device.  Every device
+// that loads the library holds its own copy until the process ends, and every
+// call on a device reuses that device's copy (the kernels overwrite what they
+// read: each workgroup clears its own partial row, every record writes its
+// staging entries, the maxima are cleared before the step and every partial
+// slice is written whole).
 static __device__ __align__(256) unsigned char scratch[WOST_NOALLOC_SCRATCH_BYTES];
 
 constexpr int kMaxScratchDevices = 64;

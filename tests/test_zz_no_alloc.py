@@ -82,7 +82,7 @@ def test_noalloc_rejects_oversized_call():
     g = W.Guide(W.GuideConfig.for_scene(s), seed=1)
     n = 1 << 24
     need = int(L.load().wost_guide_train_workspace_bytes(g.h, n))
-    assert need > (64 << 20)          # WOST_NOALLOC_SCRATCH_BYTES
+    assert need > (128 << 20)         # WOST_NOALLOC_SCRATCH_BYTES
     rec = W.Records(3, capacity=n)
     with pytest.raises(RuntimeError, match="scratch"):
         g.train_step_noalloc(rec, 0, n)
