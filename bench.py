@@ -192,7 +192,8 @@ def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2
     seeds.  Prints one JSON line per configuration."""
     import torch
 
-    def one(label, sampling="mis_learned", K=8, reflect=True, c_fixed=0.5, until=args.train_until, steps=16):
+    def one(label, sampling="mis_learned", K=8, reflect=True, c_fixed=0.5, until=args.train_until, steps=None):
+        steps = steps or args.adam_steps or 16
         rows = []
         for r in range(reps):
             seed = 500 + r
@@ -237,8 +238,16 @@ def run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args, reps=2
         one("learned c, K = %d" % K, K=K)
     for until in (128, 256):
         one("train until %d wpp" % until, until=until)
-    for steps in (8, 32):
+    base = args.adam_steps or 16
+    for steps in (base // 2, 2 * base):
         one("%d Adam steps per batch" % steps, steps=steps)
+    if args.workload == "c4":
+        # training batch size at a fixed training span (Sec. 6: larger batches
+        # block the walks longer)
+        for b in (8, 32):
+            args.batch_wpp, saved = b, args.batch_wpp
+            one("batches of %d wpp" % b)
+            args.batch_wpp = saved
 
 
 def run_engine_ab(W, online_solve, OnlineSchedule, s, geom, pts, u, args, reps=2):
@@ -601,8 +610,9 @@ def main():
     ap.add_argument("--lbvh", action="store_true",
                     help="instead of the bench line: GPU linear-BVH build and query rate against the host build")
     ap.add_argument("--ablations", action="store_true",
-                    help="instead of the bench line: sampling-mode ablations (K, selection c, reflection) and the "
-                         "training-schedule sweep on the 2D workload, one JSON line per configuration")
+                    help="instead of the bench line (C2, or C4 with --workload c4): sampling-mode ablations (K, "
+                         "selection c, reflection) and the "
+                         "training-schedule sweep, one JSON line per configuration")
     ap.add_argument("--walk-only", action="store_true",
                     help="only the timed online batches (for profiler runs): no roofline pass, guide MLP timing, "
                          "comparison or CPU baseline")
@@ -639,12 +649,21 @@ def main():
         run_lbvh(W)
         return
     if args.ablations or args.engine_ab:
-        s = scenes.scene_c2(wpp=256)
+        if args.ablations and args.workload == "c4":
+            # the 3D workload: a seeded subset of 16,384 of its points, 256
+            # walks per point, u = x^2 - y^2 in closed form
+            s = scenes.scene_c4()
+            idx = np.sort(np.random.default_rng(905).choice(s.n_points, 16384, replace=False))
+            s = s.subset(idx)
+            u = s.points[:, 0] ** 2 - s.points[:, 1] ** 2
+            args.adam_steps = args.adam_steps or 48
+        else:
+            s = scenes.scene_c2(wpp=256)
+            u = s.points[:, 0] ** 3 - 3 * s.points[:, 0] * s.points[:, 1] ** 2
         args.wpp = args.wpp or 256
         args.batch_wpp = args.batch_wpp or 16
         args.train_until = args.train_until or 64
         pts = torch.as_tensor(s.points, dtype=torch.float32, device="cuda")
-        u = s.points[:, 0] ** 3 - 3 * s.points[:, 0] * s.points[:, 1] ** 2
         geom = W.Geometry.from_scene(s)
         if args.ablations:
             run_ablations(W, OnlineSchedule, online_solve, s, geom, pts, u, args)
