@@ -224,6 +224,9 @@ template <> struct RaySetup<3> {
     }
 };
 
+// primitives of a leaf fetched together before they are tested
+constexpr int kPrimGroup = 4;
+
 template <int D> struct Prim;
 // 2D segment from one float4 (a, b)
 template <> struct Prim<2> {
@@ -406,11 +409,21 @@ __device__ __forceinline__ bool closest_dirichlet_step(const DevBvh& b, const fl
         if (!(key[k] < q.best)) break;
         const int r = comp(n.ref, k);
         const int f = leaf_first(r), c = leaf_count(r);
-        for (int j = f; j < f + c; ++j) {
-            Prim<D> pr; pr.load(b.prims, j); stat_prim(s);
-            float cp[D];
-            const float dd = pr.closest(x, cp);
-            if (dd < q.best) { q.best = dd; q.prim = j; }
+        // a leaf's primitives are fetched four at a time and then tested in
+        // order: one memory round trip per group instead of one per primitive
+        for (int j0 = f; j0 < f + c; j0 += kPrimGroup) {
+            Prim<D> pr[kPrimGroup];
+#pragma unroll
+            for (int u = 0; u < kPrimGroup; ++u)
+                if (j0 + u < f + c) pr[u].load(b.prims, j0 + u);
+#pragma unroll
+            for (int u = 0; u < kPrimGroup; ++u) {
+                if (j0 + u >= f + c) break;
+                stat_prim(s);
+                float cp[D];
+                const float dd = pr[u].closest(x, cp);
+                if (dd < q.best) { q.best = dd; q.prim = j0 + u; }
+            }
         }
     }
     float kk[4];
@@ -479,22 +492,33 @@ __device__ __forceinline__ bool cone_culls(const Box<D>& b, const float4& cone, 
 // the exact sign.  Returns the squared distance if the candidate is a
 // silhouette (adjacent primitives facing differently, or a boundary feature
 // with a single adjacent Neumann primitive), +inf otherwise.
+// the raw record of silhouette candidate k (2 float4 in 2D, 4 in 3D)
 template <int D>
-__device__ __forceinline__ float sil_prim_dist2(const float4* p, int k, const float* x, int onp)
+struct SilRec {
+    float4 s[D == 2 ? 2 : 4];
+    __device__ __forceinline__ void load(const float4* p, int k)
+    {
+#pragma unroll
+        for (int i = 0; i < (D == 2 ? 2 : 4); ++i) s[i] = p[(D == 2 ? 2 : 4) * k + i];
+    }
+};
+
+template <int D>
+__device__ __forceinline__ float sil_rec_dist2(const SilRec<D>& r, const float* x, int onp)
 {
     float a[D], n1[D], n2[D], e[D];
     int q1, q2;
     if (D == 2) {
-        const float4 s0 = p[2 * k], s1 = p[2 * k + 1];
+        const float4 s0 = r.s[0], s1 = r.s[1];
         a[0] = s0.x; a[1] = s0.y; n1[0] = s0.z; n1[1] = s0.w;
         n2[0] = s1.x; n2[1] = s1.y;
         q1 = __float_as_int(s1.z); q2 = __float_as_int(s1.w);
     } else {
-        const float4 s0 = p[4 * k], s1 = p[4 * k + 1], s2 = p[4 * k + 2], s3 = p[4 * k + 3];
-        a[0] = s0.x; a[1] = s0.y; a[2] = s0.z;
-        e[0] = s0.w - s0.x; e[1] = s1.x - s0.y; e[2] = s1.y - s0.z;
-        n1[0] = s1.z; n1[1] = s1.w; n1[2] = s2.x;
-        n2[0] = s2.y; n2[1] = s2.z; n2[2] = s2.w;
+        const float4 s0 = r.s[0], s1 = r.s[1], s2 = r.s[D == 2 ? 0 : 2], s3 = r.s[D == 2 ? 1 : 3];
+        a[0] = s0.x; a[1] = s0.y; a[2 % D] = s0.z;
+        e[0] = s0.w - s0.x; e[1] = s1.x - s0.y; e[2 % D] = s1.y - s0.z;
+        n1[0] = s1.z; n1[1] = s1.w; n1[2 % D] = s2.x;
+        n2[0] = s2.y; n2[1] = s2.z; n2[2 % D] = s2.w;
         q1 = __float_as_int(s3.x); q2 = __float_as_int(s3.y);
     }
     float w[D];
@@ -545,7 +569,18 @@ __device__ __forceinline__ bool closest_silhouette_step(const DevBvh& b, const f
         if (!(key[k] < q.best)) break;
         const int r = comp(n.ref, k);
         const int f = leaf_first(r), c = leaf_count(r);
-        for (int j = f; j < f + c; ++j) q.best = fminf(q.best, sil_prim_dist2<D>(b.prims, j, x, onp)), stat_prim(s);
+        for (int j0 = f; j0 < f + c; j0 += kPrimGroup) {
+            SilRec<D> rc[kPrimGroup];
+#pragma unroll
+            for (int u = 0; u < kPrimGroup; ++u)
+                if (j0 + u < f + c) rc[u].load(b.prims, j0 + u);
+#pragma unroll
+            for (int u = 0; u < kPrimGroup; ++u) {
+                if (j0 + u >= f + c) break;
+                q.best = fminf(q.best, sil_rec_dist2<D>(rc[u], x, onp));
+                stat_prim(s);
+            }
+        }
     }
     float kk[4];
 #pragma unroll
