@@ -182,11 +182,12 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
 
     for (int c = lane; c < N; c += kWave) pv.i(F::STAT, base + c) = ST_EMPTY;
     wave_sync();
+    int Nn = N;  // scanned prefix of the pool (shrinks once no new walks come)
 
     for (;;) {
         // ---- step update of last round's walks, retirement, refill
         int n_act = 0;
-        for (int c0 = 0; c0 < N; c0 += kWave) {
+        for (int c0 = 0; c0 < Nn; c0 += kWave) {
             const int li = c0 + lane;
             const uint32_t g = base + li;
             int stt = pv.i(F::STAT, g);
@@ -343,6 +344,33 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             n_act += __popcll(am);
         }
         if (n_act == 0 && exhausted) break;
+        // ---- once no new walks come, move the live walks to the front of
+        // the pool whenever they fill at most half of the scanned prefix, so
+        // that the last rounds scan a few chunks instead of the whole pool.
+        // L_act is increasing, so a slot is only ever read by a list entry at
+        // or before the one that overwrites it: within a chunk every lane's
+        // load of a word returns before that word's store is issued, and
+        // later chunks read slots beyond every earlier destination.  Walks
+        // keep their ids and random streams, so every estimate is unchanged.
+        if (exhausted && Nn > kWave && 2 * n_act <= Nn) {
+            wave_sync();
+            for (int r0 = 0; r0 < n_act; r0 += kWave) {
+                const int r = r0 + lane;
+                const int src = r < n_act ? L_act[r] : r;
+                if (src != r) {
+#pragma unroll 4
+                    for (int f = 0; f < F::WORDS; ++f) {
+                        const uint32_t v = pv.u(f, base + src);
+                        pv.u(f, base + r) = v;
+                    }
+                }
+            }
+            const int n_new = (n_act + kWave - 1) / kWave * kWave;
+            for (int r = n_act + lane; r < n_new; r += kWave) pv.i(F::STAT, base + r) = ST_EMPTY;
+            wave_sync();
+            for (int r = lane; r < n_act; r += kWave) L_act[r] = r;
+            Nn = n_new;
+        }
         wave_sync();
 
         // ---- closest Dirichlet point; epsilon-shell and step-cap termination
@@ -387,7 +415,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
         // the walks that step on; the star's queries run longer far from the
         // Dirichlet boundary (a larger search radius) and on the Neumann
         // boundary, where normal cones prune less
-        n_step = list_long_first(L_step, N, base, lane, [&](uint32_t g) { return pv.i(F::STAT, g) == ST_STEP; },
+        n_step = list_long_first(L_step, Nn, base, lane, [&](uint32_t g) { return pv.i(F::STAT, g) == ST_STEP; },
                                  [&](uint32_t g) { return pv.f(F::DD, g) * (pv.i(F::ONP, g) >= 0 ? 2.f : 1.f); });
         wave_sync();
         if (n_step == 0) continue;
