@@ -756,7 +756,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WOST_WAVES_2
 #define WOST_WAVES_3D_UNIFORM 3
 #endif
 #ifndef WOST_WAVES_3D_GUIDED
-#define WOST_WAVES_3D_GUIDED 2
+#define WOST_WAVES_3D_GUIDED 3
 #endif
 template <bool STATS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(WOST_WAVES_3D_UNIFORM))) void walk_kernel3u(const WalkParams P)
