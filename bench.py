@@ -526,9 +526,12 @@ def compare_guided_uniform(W, wl, seed=900, n_ref=4096, ref_wpp=2048):
 def walk_roofline(W, wl, guide, total_steps, walk_s, n_launch):
     """Roofline position of the guided walk kernel: algorithmic bytes per step
     (nodes and primitives the six queries of a step read, counted by the
-    instrumented kernel on a sample of the workload) against the average
-    launch duration; the HBM bytes per launch measured by counters where the
-    committed counter summary matches the sources built here."""
+    instrumented kernel on one launch of the timed shape: every point of the
+    workload at the batch's walks per point, so that the per-query iteration
+    overhead over a packed wave includes the end of a launch as the timed
+    batches see it) against the average launch duration; the HBM bytes per
+    launch measured by counters where the committed counter summary matches
+    the sources built here."""
     import torch
 
     from paper_2410_18944_amd import api
@@ -537,8 +540,7 @@ def walk_roofline(W, wl, guide, total_steps, walk_s, n_launch):
     d = s.dim
     cost = torch.zeros(18, dtype=torch.int64, device="cuda")
     api.set_cost_counters(cost)
-    sample = pts[:: max(1, s.n_points // 8192)]
-    a_g = W.solve(wl["geom"], wl["pb_g"], sample, 16, seed=5, guide=guide)
+    a_g = W.solve(wl["geom"], wl["pb_g"], pts, wl["batch_wpp"], seed=5, guide=guide)
     torch.cuda.synchronize()
     api.set_cost_counters(None)
     cost_g = api.cost_report(cost, a_g.stats()["steps"])
@@ -555,7 +557,8 @@ def walk_roofline(W, wl, guide, total_steps, walk_s, n_launch):
            "walk_sources_sha256": walk_sources_sha256()[:16],
            "nodes_per_step": {q: round(c["nodes_per_step"], 2) for q, c in cost_g.items()},
            "prims_per_step": {q: round(c["prims_per_step"], 2) for q, c in cost_g.items()},
-           # wave iterations over perfectly packed ones (64 x wave iterations / lane node visits)
+           # wave iterations over perfectly packed ones (64 x wave iterations / lane node visits):
+           # 64 / this is the mean number of lanes that advance a query per iteration
            "iterations_vs_packed": {q: round(c["divergence"], 2) for q, c in cost_g.items()}}
     if tr:
         # counter figures per launch (committed summary of the same kernel on

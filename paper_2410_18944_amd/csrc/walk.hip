@@ -329,6 +329,7 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
                             pv.i(F::ONP, g) = -1;
                             pv.f(F::T, g) = 1.f;
                             pv.f(F::ACC, g) = 0.f;
+                            pv.f(F::DD, g) = 0.f;
                             pv.i(F::K, g) = 0;
                             pv.u(F::WLO, g) = (uint32_t)id;
                             pv.u(F::WHI, g) = (uint32_t)(id >> 32);
@@ -372,6 +373,15 @@ __device__ __forceinline__ void walk_body(const WalkParams& P)
             Nn = n_new;
         }
         wave_sync();
+        // In 3D a closest-point query's length grows with the distance to the
+        // Dirichlet boundary (the search ball), and the phase waits for its
+        // longest query: list the walks whose last distance was at least the
+        // mean first, so that those start early.  New walks count as short.
+        if constexpr (D == 3) {
+            list_long_first(L_act, Nn, base, lane, [&](uint32_t g) { return pv.i(F::STAT, g) == ST_ACTIVE; },
+                            [&](uint32_t g) { return pv.f(F::DD, g); });
+            wave_sync();
+        }
 
         // ---- closest Dirichlet point; epsilon-shell and step-cap termination
         int n_step = 0;
