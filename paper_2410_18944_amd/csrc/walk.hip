@@ -48,7 +48,11 @@ static inline size_t walk_lds_bytes(bool guided, int stack_entries, int out_stri
 // its visibility, source point and its visibility, first hit, then the step
 // update.  Inside a traversal phase a lane whose query has finished takes the
 // next walk of that phase's list at once, so the wave does not wait for its
-// slowest lane; lanes of a phase all run the same query code.
+// slowest lane; lanes of a phase all run the same query code.  Phases whose
+// query length can be predicted from the pool (closest Dirichlet point in 3D,
+// closest silhouette) hand out their longest queries first.  Once the wave
+// can start no new walks it moves its live walks to the front of the pool, so
+// the last rounds scan only the occupied slots.
 
 // Lanes that have finished their query wait until at least this many are
 // waiting (or no lane is still traversing) before they store results and
