@@ -1,9 +1,10 @@
 """Benchmark: guided vs uniform walk on stars on one MI355X.
 
 Default workload: the 3D Poisson problem at scale -- a seeded noise-displaced
-sphere of 1,003,520 triangles with three spherical holes, Neumann data on the
-upper half of the outer surface, Dirichlet data x^2 - y^2 elsewhere, a source
-of 16 seeded Gaussian bumps, 2^20 random interior query points.  One timed
+sphere of 1,003,520 triangles with three spherical holes (1,018,880 triangles
+in all), Neumann data on the upper half of the outer surface, Dirichlet data
+x^2 - y^2 elsewhere, a source of 16 seeded Gaussian bumps, 2^20 random
+interior query points.  One timed
 step is one training batch of the online guided solve: 4 walks per point
 (2^22 walks, guide frozen, every drawn direction recorded), the tail pass,
 the batch's training set drawn from its records and the Adam steps on the
